@@ -1,0 +1,23 @@
+"""FP64 CPU oracle for radiative-transport flame volume reconstruction.
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It is independent of
+the HIP library: no shared code, headers or tables; the only common module is
+the seeded input generator ``synth``.
+
+The arithmetic lives in ``rte_oracle.c`` (plain C, double precision); this
+module marshals numpy arrays into it with ctypes.
+
+Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``):
+  ray_table            pinned (chord closed forms, symmetry, point projection)
+  render               pinned (Beer-Lambert, sigma = 0 affine line integral,
+                       fine-quadrature limit, 90-degree symmetry, point projection)
+  inscatter            pinned (closed form for constant fields, sigma = 0 limit)
+  backproject_adjoint  pinned (adjoint identity, dense-matrix transpose)
+  backproject_paper    pinned (hand-computed single-ray worked case)
+  reconstruct          pinned (dense least-squares recovery, SIRT monotone residual)
+  planck / band / lut  pinned (Stefan-Boltzmann integral, Wien peak, LUT vs
+                       direct integral within the interpolation bound)
+  temperature_fit      pinned (fixed point at the true temperature)
+"""
+from .oracle import *  # noqa: F401,F403

@@ -1,0 +1,787 @@
+/*
+ * rte_oracle.c -- plain, slow, FP64 CPU oracle for radiative-transport
+ * flame volume reconstruction (Shen et al., "Radiative Transport Based
+ * Flame Volume Reconstruction from Videos", arXiv:1809.06417).
+ *
+ * TEST INFRASTRUCTURE ONLY. The test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only users of this library. It
+ * shares no source, header, table or helper with the HIP library, and the
+ * HIP library never loads it.
+ *
+ * Every function follows a passage of the paper; where the paper is silent
+ * the reading used is stated next to the code. Arithmetic is double
+ * precision throughout. Parallel loops (OpenMP) only split independent rays
+ * or key points; every sum that crosses threads is reduced in a fixed
+ * thread order, so results are reproducible for a given thread count.
+ *
+ * Conventions (shared with the callers, not with the GPU code):
+ *  - Grid: n[a] key points per axis a (x, y, z) at the voxel vertices
+ *    (Sec. 3.3, "Key points"), spanning [lo, hi]; fields are stored
+ *    [z][y][x] with x fastest. h_a = (hi_a - lo_a) / (n_a - 1).
+ *  - Camera: x_c = R x_w + t, pixel (u, v) centre at (u + 1/2, v + 1/2),
+ *    u to the right, v downwards, optical axis +z_c (pinhole perspective
+ *    projection, Sec. 3.2 and Sec. 4.1).
+ *  - Images: [view][channel][v][u]. Volumes: [channel][z][y][x].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double fx, fy, cx, cy;
+    double R[9]; /* row-major world -> camera rotation */
+    double t[3];
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    int32_t n[3]; /* key points along x, y, z */
+    double lo[3], hi[3];
+} orc_grid;
+
+typedef struct {
+    double t_min, t_max;  /* LUT domain [K] */
+    double t_norm;        /* normalising temperature [K] */
+    double band_nm[3];    /* camera band centres, R G B [nm] */
+    double band_std_nm;   /* Gaussian band standard deviation [nm] */
+    int32_t lut_size;
+    double sigma_max;     /* extinction at full soot load [1/unit length] */
+    double soot_t0;       /* soot appears above this temperature [K] */
+    double soot_span;     /* soot load reaches 1 at soot_t0 + soot_span [K] */
+    int32_t channel;      /* channel used for the fit (1 = green) */
+    int32_t panels;       /* Simpson panels for each band integral */
+} orc_temp_params;
+
+#define ORC_MAX_THREADS 32
+
+static int n_threads(void)
+{
+#ifdef _OPENMP
+    int t = omp_get_max_threads();
+    return t > ORC_MAX_THREADS ? ORC_MAX_THREADS : (t < 1 ? 1 : t);
+#else
+    return 1;
+#endif
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* ---------------------------------------------------------------- grid */
+
+static long grid_nodes(const orc_grid *g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
+
+static void grid_spacing(const orc_grid *g, double h[3])
+{
+    for (int a = 0; a < 3; ++a) h[a] = (g->hi[a] - g->lo[a]) / (double)(g->n[a] - 1);
+}
+
+static double grid_min_spacing(const orc_grid *g)
+{
+    double h[3];
+    grid_spacing(g, h);
+    double m = h[0];
+    if (h[1] < m) m = h[1];
+    if (h[2] < m) m = h[2];
+    return m;
+}
+
+/* Trilinear stencil of a point (Sec. 3.3: a sample point touches its eight
+ * neighbouring key points). q holds grid coordinates (units of h); they are
+ * clamped to [0, n-1] and the cell index to n-2, so the stencil always has
+ * eight valid corners. idx/w receive the corners in (dz, dy, dx) binary
+ * order. */
+static void stencil(const orc_grid *g, const double q[3], long idx[8], double w[8], double frac[3],
+                    int cell[3])
+{
+    double f[3];
+    int i[3];
+    for (int a = 0; a < 3; ++a) {
+        double c = q[a];
+        double top = (double)(g->n[a] - 1);
+        if (c < 0.0) c = 0.0;
+        if (c > top) c = top;
+        int ia = (int)floor(c);
+        if (ia > g->n[a] - 2) ia = g->n[a] - 2;
+        i[a] = ia;
+        f[a] = c - (double)ia;
+    }
+    long nx = g->n[0], nxy = (long)g->n[0] * g->n[1];
+    for (int corner = 0; corner < 8; ++corner) {
+        int dx = corner & 1, dy = (corner >> 1) & 1, dz = (corner >> 2) & 1;
+        idx[corner] = (long)(i[2] + dz) * nxy + (long)(i[1] + dy) * nx + (i[0] + dx);
+        w[corner] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+    }
+    if (frac) for (int a = 0; a < 3; ++a) frac[a] = f[a];
+    if (cell) for (int a = 0; a < 3; ++a) cell[a] = i[a];
+}
+
+static double trilerp(const orc_grid *g, const double *field, const double q[3])
+{
+    long idx[8];
+    double w[8];
+    stencil(g, q, idx, w, NULL, NULL);
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) s += w[c] * field[idx[c]];
+    return s;
+}
+
+static void to_grid_coords(const orc_grid *g, const double p[3], double q[3])
+{
+    double h[3];
+    grid_spacing(g, h);
+    for (int a = 0; a < 3; ++a) q[a] = (p[a] - g->lo[a]) / h[a];
+}
+
+/* ------------------------------------------------------------- cameras */
+
+/* Pinhole ray through the centre of pixel (u, v): origin at the camera
+ * centre -R^T t, unit direction R^T K^{-1} (u + 1/2, v + 1/2, 1)^T. */
+static void camera_ray(const orc_camera *c, int u, int v, double o[3], double d[3])
+{
+    double dc[3] = {((double)u + 0.5 - c->cx) / c->fx, ((double)v + 0.5 - c->cy) / c->fy, 1.0};
+    double n2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        d[i] = c->R[0 * 3 + i] * dc[0] + c->R[1 * 3 + i] * dc[1] + c->R[2 * 3 + i] * dc[2];
+        o[i] = -(c->R[0 * 3 + i] * c->t[0] + c->R[1 * 3 + i] * c->t[1] + c->R[2 * 3 + i] * c->t[2]);
+        n2 += d[i] * d[i];
+    }
+    double inv = 1.0 / sqrt(n2);
+    for (int i = 0; i < 3; ++i) d[i] *= inv;
+}
+
+/* Entry/exit of the ray o + t d (t >= 0) through the box [lo, hi] (slab
+ * method). Returns 1 when the ray crosses a segment of positive length. */
+static int ray_box(const double lo[3], const double hi[3], const double o[3], const double d[3],
+                   double *tn, double *tf)
+{
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0) {
+            double ta = (lo[a] - o[a]) / d[a], tb = (hi[a] - o[a]) / d[a];
+            if (ta > tb) { double s = ta; ta = tb; tb = s; }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        } else if (o[a] < lo[a] || o[a] > hi[a]) {
+            return 0;
+        }
+    }
+    if (t0 < 0.0) t0 = 0.0;
+    *tn = t0;
+    *tf = t1;
+    return t1 > t0;
+}
+
+/* Segments of a chord [tn, tf] with step ds (Sec. 4.2: samples spaced at a
+ * fixed step along each ray). K = ceil((tf - tn) / ds); segment k spans
+ * [tn + k ds, min(tn + (k+1) ds, tf)] and its sample sits at the midpoint,
+ * so the last segment is clipped at the exit. */
+static int n_segments(double tn, double tf, double ds)
+{
+    if (!(tf > tn)) return 0;
+    return (int)ceil((tf - tn) / ds);
+}
+
+static void segment(double tn, double tf, double ds, int k, double *tmid, double *len)
+{
+    double a = tn + (double)k * ds;
+    double b = tn + (double)(k + 1) * ds;
+    if (b > tf) b = tf;
+    if (b < a) b = a;
+    *len = b - a;
+    *tmid = 0.5 * (a + b);
+}
+
+/* phi(x) = (1 - e^{-x}) / x, phi(0) = 1: exact integral of the transmittance
+ * over a segment of optical thickness x, divided by x. */
+static double phi(double x)
+{
+    if (x == 0.0) return 1.0;
+    return -expm1(-x) / x;
+}
+
+static int camera_index_ok(const orc_camera *c) { return c->width > 0 && c->height > 0; }
+
+/* --------------------------------------------------------------- rays */
+
+/* Ray table: entry distance, exit distance and number of segments of every
+ * pixel ray, in [view][v][u] order. Misses get K = 0 and t_near = t_far = 0. */
+int orc_ray_table(const orc_grid *g, const orc_camera *cams, int32_t V, double step_vox,
+                  double *t_near, double *t_far, int32_t *K)
+{
+    double ds = step_vox * grid_min_spacing(g);
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        if (!camera_index_ok(c)) return -1;
+        long base = (long)v * c->width * c->height;
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < (long)c->width * c->height; ++p) {
+            int u = (int)(p % c->width), vv = (int)(p / c->width);
+            double o[3], d[3], tn, tf;
+            camera_ray(c, u, vv, o, d);
+            if (ray_box(g->lo, g->hi, o, d, &tn, &tf)) {
+                t_near[base + p] = tn;
+                t_far[base + p] = tf;
+                K[base + p] = n_segments(tn, tf, ds);
+            } else {
+                t_near[base + p] = 0.0;
+                t_far[base + p] = 0.0;
+                K[base + p] = 0;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- render */
+
+/* Emission-absorption(-in-scattering) render of every pixel of every view.
+ *
+ * Eq. 5 along one ray, with the optical model of Eq. 6, integrated exactly
+ * for piecewise-constant extinction and source on each segment and composed
+ * front to back as in Eq. 7-8 (segment opacity 1 - e^{-sigma Delta}, segment
+ * radiance j / sigma):
+ *   I_c = sum_k T_k j_kc Delta_k phi(sigma_k Delta_k) + T_K L_bg,
+ *   T_{k+1} = T_k e^{-sigma_k Delta_k},  T_0 = 1,
+ *   j_kc = eps_c(x_k) + albedo * sigma(x_k) * S_c(x_k),
+ *   sigma(x) = max(0, trilinear extinction).
+ * The emission field is the emitted colour intensity itself (Sec. 3.3,
+ * "Emission"). S (in-scattered radiance, Eq. 5 third term) is a grid of
+ * s_res^3 nodes over the same box, or NULL.
+ *
+ * em [C][N], sig [N], S [C][s_res^3] or NULL, img [V][C][H][W].
+ * rowsum [V][H][W] (optional) receives sum_k T_k Delta_k phi_k. */
+int orc_render(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
+               double albedo, double background, const double *em, const double *sig,
+               int32_t s_res, const double *S, double *img, double *rowsum)
+{
+    if (C < 1) return -1;
+    double ds = step_vox * grid_min_spacing(g);
+    long N = grid_nodes(g);
+    orc_grid sg;
+    if (S) {
+        for (int a = 0; a < 3; ++a) { sg.n[a] = s_res; sg.lo[a] = g->lo[a]; sg.hi[a] = g->hi[a]; }
+    }
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        if (!camera_index_ok(c)) return -1;
+        long HW = (long)c->width * c->height;
+#pragma omp parallel for schedule(static)
+        for (long p = 0; p < HW; ++p) {
+            int u = (int)(p % c->width), vv = (int)(p / c->width);
+            double o[3], d[3], tn, tf;
+            double I[16];
+            for (int ch = 0; ch < C; ++ch) I[ch] = 0.0;
+            double T = 1.0, R = 0.0;
+            camera_ray(c, u, vv, o, d);
+            if (ray_box(g->lo, g->hi, o, d, &tn, &tf)) {
+                int K = n_segments(tn, tf, ds);
+                for (int k = 0; k < K; ++k) {
+                    double t, len, x[3], q[3];
+                    segment(tn, tf, ds, k, &t, &len);
+                    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+                    to_grid_coords(g, x, q);
+                    double s = trilerp(g, sig, q);
+                    if (s < 0.0) s = 0.0;
+                    double wgt = T * len * phi(s * len);
+                    for (int ch = 0; ch < C; ++ch) {
+                        double j = trilerp(g, em + (long)ch * N, q);
+                        if (S && albedo != 0.0) {
+                            double qs[3];
+                            to_grid_coords(&sg, x, qs);
+                            j += albedo * s * trilerp(&sg, S + (long)ch * s_res * s_res * s_res, qs);
+                        }
+                        I[ch] += wgt * j;
+                    }
+                    R += wgt;
+                    T *= exp(-s * len);
+                }
+            }
+            for (int ch = 0; ch < C; ++ch)
+                img[((long)v * C + ch) * HW + p] = I[ch] + T * background;
+            if (rowsum) rowsum[(long)v * HW + p] = R;
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------- in-scatter */
+
+/* Spherical Fibonacci direction d of n (unit vector). */
+static void fib_dir(int d, int n, double u[3])
+{
+    double z = 1.0 - (2.0 * d + 1.0) / (double)n;
+    double r = sqrt(fmax(0.0, 1.0 - z * z));
+    double ph = (double)d * M_PI * (3.0 - sqrt(5.0));
+    u[0] = r * cos(ph);
+    u[1] = r * sin(ph);
+    u[2] = z;
+}
+
+/* In-scattered radiance grid (Eq. 5 third term with the isotropic phase
+ * function of Eq. 9 at g = 0, so the scattering integral is the mean
+ * incident radiance). At each of the s_res^3 nodes p of a grid over the same
+ * box:
+ *   S_c(p) = (1/n_dirs) sum_d L_c(p <- u_d),
+ *   L_c(p <- u) = emission-absorption march from p along u to the box exit,
+ * with n_dirs spherical-Fibonacci directions, segments of
+ * s_step * (coarse node spacing) and the same segment rule as the render.
+ * Single scattering: the march uses the emission only. */
+int orc_inscatter(const orc_grid *g, int32_t C, const double *em, const double *sig, int32_t s_res,
+                  int32_t n_dirs, double s_step, double *S)
+{
+    if (s_res < 2 || n_dirs < 1) return -1;
+    long N = grid_nodes(g);
+    orc_grid sg;
+    for (int a = 0; a < 3; ++a) { sg.n[a] = s_res; sg.lo[a] = g->lo[a]; sg.hi[a] = g->hi[a]; }
+    double hs[3];
+    grid_spacing(&sg, hs);
+    double ds = s_step * grid_min_spacing(&sg);
+    long M3 = (long)s_res * s_res * s_res;
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < M3; ++m) {
+        int mx = (int)(m % s_res), my = (int)((m / s_res) % s_res), mz = (int)(m / ((long)s_res * s_res));
+        double p[3] = {g->lo[0] + mx * hs[0], g->lo[1] + my * hs[1], g->lo[2] + mz * hs[2]};
+        double acc[16];
+        for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
+        for (int dd = 0; dd < n_dirs; ++dd) {
+            double u[3], tn, tf;
+            fib_dir(dd, n_dirs, u);
+            if (!ray_box(g->lo, g->hi, p, u, &tn, &tf)) continue;
+            int K = n_segments(tn, tf, ds);
+            double T = 1.0;
+            for (int k = 0; k < K; ++k) {
+                double t, len, x[3], q[3];
+                segment(tn, tf, ds, k, &t, &len);
+                for (int a = 0; a < 3; ++a) x[a] = p[a] + t * u[a];
+                to_grid_coords(g, x, q);
+                double s = trilerp(g, sig, q);
+                if (s < 0.0) s = 0.0;
+                double wgt = T * len * phi(s * len);
+                for (int ch = 0; ch < C; ++ch) acc[ch] += wgt * trilerp(g, em + (long)ch * N, q);
+                T *= exp(-s * len);
+            }
+        }
+        for (int ch = 0; ch < C; ++ch) S[(long)ch * M3 + m] = acc[ch] / (double)n_dirs;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------ back-projection */
+
+static double *alloc_private(int nt, long n)
+{
+    return (double *)calloc((size_t)nt * (size_t)n, sizeof(double));
+}
+
+static void reduce_private(const double *priv, int nt, long n, double *out)
+{
+    for (long i = 0; i < n; ++i) out[i] = 0.0;
+    for (int t = 0; t < nt; ++t)
+        for (long i = 0; i < n; ++i) out[i] += priv[(long)t * n + i];
+}
+
+/* Transpose of the linear emission -> image map A of orc_render (extinction
+ * fixed, no in-scattering, no background):
+ *   delta_c[j] = sum_rays sum_k res_c(ray) * T_k Delta_k phi_k * w_j(x_k),
+ * w_j = trilinear weight of key point j at sample x_k. Written as a scatter
+ * over rays and samples into per-thread private accumulators (Alg. 2 adds
+ * the adjustment of the eight key points of every sample). res
+ * [V][C][H][W], delta [C][N]. */
+int orc_backproject_adjoint(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C,
+                            double step_vox, const double *sig, const double *res, double *delta)
+{
+    double ds = step_vox * grid_min_spacing(g);
+    long N = grid_nodes(g);
+    int nt = n_threads();
+    double *priv = alloc_private(nt, (long)C * N);
+    if (!priv) return -2;
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        long HW = (long)c->width * c->height;
+#pragma omp parallel num_threads(nt)
+        {
+            double *acc = priv + (long)thread_id() * C * N;
+#pragma omp for schedule(static)
+            for (long p = 0; p < HW; ++p) {
+                int u = (int)(p % c->width), vv = (int)(p / c->width);
+                double o[3], d[3], tn, tf;
+                camera_ray(c, u, vv, o, d);
+                if (!ray_box(g->lo, g->hi, o, d, &tn, &tf)) continue;
+                int K = n_segments(tn, tf, ds);
+                double T = 1.0;
+                for (int k = 0; k < K; ++k) {
+                    double t, len, x[3], q[3], w[8];
+                    long idx[8];
+                    segment(tn, tf, ds, k, &t, &len);
+                    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+                    to_grid_coords(g, x, q);
+                    double s = trilerp(g, sig, q);
+                    if (s < 0.0) s = 0.0;
+                    double gw = T * len * phi(s * len);
+                    stencil(g, q, idx, w, NULL, NULL);
+                    for (int ch = 0; ch < C; ++ch) {
+                        double y = res[((long)v * C + ch) * HW + p];
+                        for (int cr = 0; cr < 8; ++cr) acc[(long)ch * N + idx[cr]] += y * gw * w[cr];
+                    }
+                    T *= exp(-s * len);
+                }
+            }
+        }
+    }
+    reduce_private(priv, nt, (long)C * N, delta);
+    free(priv);
+    return 0;
+}
+
+/* Paper's adjustment (Eq. 10-12 with G(s) = 1): every sample s of every ray
+ * adds to each of its eight neighbouring key points j
+ *   A_js = alpha_l * dL(x, y) * (1 - tau)^k * exp(-alpha_d * D(j, s)),
+ * with dL the colour residual of the ray's pixel (source minus rendered),
+ * k the 0-based order of the sample counted from the ray's entry into the
+ * volume (Eq. 12 with its exponent k - 1 for 1-based order) and D the
+ * Euclidean distance in voxel units. dL [V][C][H][W], delta [C][N]. */
+int orc_backproject_paper(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C,
+                          double step_vox, double alpha_l, double alpha_d, double tau,
+                          const double *dL, double *delta)
+{
+    double ds = step_vox * grid_min_spacing(g);
+    long N = grid_nodes(g);
+    int nt = n_threads();
+    double *priv = alloc_private(nt, (long)C * N);
+    if (!priv) return -2;
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        long HW = (long)c->width * c->height;
+#pragma omp parallel num_threads(nt)
+        {
+            double *acc = priv + (long)thread_id() * C * N;
+#pragma omp for schedule(static)
+            for (long p = 0; p < HW; ++p) {
+                int u = (int)(p % c->width), vv = (int)(p / c->width);
+                double o[3], d[3], tn, tf;
+                camera_ray(c, u, vv, o, d);
+                if (!ray_box(g->lo, g->hi, o, d, &tn, &tf)) continue;
+                int K = n_segments(tn, tf, ds);
+                for (int k = 0; k < K; ++k) {
+                    double t, len, x[3], q[3], w[8], f[3];
+                    long idx[8];
+                    int cell[3];
+                    segment(tn, tf, ds, k, &t, &len);
+                    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+                    to_grid_coords(g, x, q);
+                    stencil(g, q, idx, w, f, cell);
+                    double tr = pow(1.0 - tau, (double)k);
+                    for (int cr = 0; cr < 8; ++cr) {
+                        double ddx = f[0] - (double)(cr & 1);
+                        double ddy = f[1] - (double)((cr >> 1) & 1);
+                        double ddz = f[2] - (double)((cr >> 2) & 1);
+                        double D = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+                        double a = alpha_l * tr * exp(-alpha_d * D);
+                        for (int ch = 0; ch < C; ++ch)
+                            acc[(long)ch * N + idx[cr]] += a * dL[((long)v * C + ch) * HW + p];
+                    }
+                }
+            }
+        }
+    }
+    reduce_private(priv, nt, (long)C * N, delta);
+    free(priv);
+    return 0;
+}
+
+/* ------------------------------------------------------ reconstruction */
+
+static long images_size(const orc_camera *cams, int V, int C)
+{
+    return (long)V * C * cams[0].width * cams[0].height;
+}
+
+/* Iterative reconstruction of the emission (Sec. 3 overview: start from the
+ * given volume, render, compare with the frames, adjust, repeat; Alg. 2).
+ * R = A 1 (row sums) and Cs = A^T 1 (column sums) of the linear emission ->
+ * image map A at the fixed extinction; rows and columns with zero sum are
+ * skipped. I(e) is the full render including in-scattering, whose grid S is
+ * recomputed from the current volume at the start of every iteration and
+ * held fixed within it.
+ *
+ * mode 0, SART (simultaneous over all views, i.e. SIRT):
+ *   e <- e + lambda * Cs^{-1} A^T R^{-1} (F - I(e)), optionally clamped at 0.
+ * mode 1, the paper's adjustment (Eq. 10-11, G = 1):
+ *   e <- e + delta_paper(F - I(e)), optionally clamped at 0.
+ * mode 2, multiplicative EM update (ML-EM, Shepp and Vardi 1982):
+ *   e <- e * (1 + lambda * (A^T q / Cs - 1)),  q = F / I(e) on rays with
+ *   I > 0 and q = 1 elsewhere.
+ * frames [V][C][H][W], sig [N], em_io [C][N].
+ * resid_out (optional, [iters]) receives sum (F - I)^2 before each update. */
+int orc_reconstruct(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C,
+                    double step_vox, double albedo, double background, int32_t s_res,
+                    int32_t n_dirs, double s_step, const double *frames, const double *sig,
+                    double *em_io, int32_t iters, int32_t mode, double lambda,
+                    int32_t clamp_nonneg, double alpha_l, double alpha_d, double tau,
+                    double *resid_out)
+{
+    long N = grid_nodes(g);
+    long NI = images_size(cams, V, C);
+    long HW = (long)cams[0].width * cams[0].height;
+    for (int v = 1; v < V; ++v)
+        if (cams[v].width != cams[0].width || cams[v].height != cams[0].height) return -1;
+    double *img = (double *)malloc(sizeof(double) * NI);
+    double *y = (double *)malloc(sizeof(double) * NI);
+    double *delta = (double *)malloc(sizeof(double) * C * N);
+    double *rows = (double *)malloc(sizeof(double) * V * HW);
+    double *cols = (double *)malloc(sizeof(double) * N);
+    double *ones_n = (double *)malloc(sizeof(double) * N);
+    double *ones_img = (double *)malloc(sizeof(double) * V * HW);
+    long M3 = (long)s_res * s_res * s_res;
+    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * C * M3) : NULL;
+    int rc = 0;
+    if (!img || !y || !delta || !rows || !cols || !ones_n || !ones_img ||
+        (albedo != 0.0 && s_res >= 2 && !S)) { rc = -2; goto done; }
+
+    if (mode == 0 || mode == 2) {
+        /* R = A 1 and Cs = A^T 1 for the fixed extinction. */
+        for (long i = 0; i < N; ++i) ones_n[i] = 1.0;
+        for (long i = 0; i < V * HW; ++i) ones_img[i] = 1.0;
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, rows, NULL);
+        if (rc) goto done;
+        rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, ones_img, cols);
+        if (rc) goto done;
+    }
+    for (int it = 0; it < iters; ++it) {
+        if (S) {
+            rc = orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
+            if (rc) goto done;
+        }
+        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, img, NULL);
+        if (rc) goto done;
+        double r2 = 0.0;
+        for (long i = 0; i < NI; ++i) {
+            double r = frames[i] - img[i];
+            r2 += r * r;
+        }
+        if (resid_out) resid_out[it] = r2;
+        if (mode == 0 || mode == 2) {
+            for (int v = 0; v < V; ++v)
+                for (int ch = 0; ch < C; ++ch)
+                    for (long p = 0; p < HW; ++p) {
+                        long i = ((long)v * C + ch) * HW + p;
+                        double R = rows[(long)v * HW + p];
+                        if (mode == 0)
+                            y[i] = R > 0.0 ? (frames[i] - img[i]) / R : 0.0;
+                        else
+                            y[i] = img[i] > 0.0 ? frames[i] / img[i] : 1.0;
+                    }
+            rc = orc_backproject_adjoint(g, cams, V, C, step_vox, sig, y, delta);
+            if (rc) goto done;
+            for (int ch = 0; ch < C; ++ch)
+                for (long j = 0; j < N; ++j) {
+                    if (!(cols[j] > 0.0)) continue;
+                    double e = em_io[(long)ch * N + j];
+                    if (mode == 0)
+                        e += lambda * delta[(long)ch * N + j] / cols[j];
+                    else
+                        e *= 1.0 + lambda * (delta[(long)ch * N + j] / cols[j] - 1.0);
+                    if (clamp_nonneg && e < 0.0) e = 0.0;
+                    em_io[(long)ch * N + j] = e;
+                }
+        } else {
+            for (long i = 0; i < NI; ++i) y[i] = frames[i] - img[i];
+            rc = orc_backproject_paper(g, cams, V, C, step_vox, alpha_l, alpha_d, tau, y, delta);
+            if (rc) goto done;
+            for (long i = 0; i < (long)C * N; ++i) {
+                double e = em_io[i] + delta[i];
+                if (clamp_nonneg && e < 0.0) e = 0.0;
+                em_io[i] = e;
+            }
+        }
+    }
+done:
+    free(img); free(y); free(delta); free(rows); free(cols); free(ones_n); free(ones_img); free(S);
+    return rc;
+}
+
+/* --------------------------------------------------------- temperature */
+
+/* Planck's law (Eq. 13): spectral radiance of a black body at wavelength
+ * lambda [m] and temperature T [K], with exact SI constants and the vacuum
+ * speed of light (the flame's refractive index is taken as 1). */
+double orc_planck(double lambda, double T)
+{
+    const double h = 6.62607015e-34, c = 2.99792458e8, kb = 1.380649e-23;
+    double x = h * c / (lambda * kb * T);
+    return 2.0 * h * c * c / pow(lambda, 5.0) / expm1(x);
+}
+
+/* Band radiance: integral of B(lambda, T) * exp(-(lambda - mu)^2 / (2 s^2))
+ * over [mu - 6 s, mu + 6 s] by composite Simpson with `panels` panels
+ * (rounded up to even). mu, s in nm; the result is per metre of
+ * wavelength times nm. */
+double orc_band_radiance(double T, double mu_nm, double std_nm, int32_t panels)
+{
+    if (panels < 2) panels = 2;
+    if (panels & 1) ++panels;
+    double a = mu_nm - 6.0 * std_nm, b = mu_nm + 6.0 * std_nm;
+    double hstep = (b - a) / panels, s = 0.0;
+    for (int i = 0; i <= panels; ++i) {
+        double l = a + i * hstep;
+        double z = (l - mu_nm) / std_nm;
+        double f = orc_planck(l * 1e-9, T) * exp(-0.5 * z * z);
+        double wgt = (i == 0 || i == panels) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        s += wgt * f;
+    }
+    return s * hstep / 3.0;
+}
+
+/* Colour-temperature mapping (Sec. 3.3 "Temperature Reconstruction"):
+ * B_c(T) = band_c(T) / band_ch(t_norm), tabulated at lut_size temperatures
+ * evenly spaced over [t_min, t_max]. lut [3][lut_size]. */
+int orc_temp_lut(const orc_temp_params *tp, double *lut)
+{
+    int L = tp->lut_size;
+    if (L < 2) return -1;
+    double norm = orc_band_radiance(tp->t_norm, tp->band_nm[tp->channel], tp->band_std_nm, tp->panels);
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < L; ++i) {
+            double T = tp->t_min + (tp->t_max - tp->t_min) * (double)i / (double)(L - 1);
+            lut[(long)c * L + i] = orc_band_radiance(T, tp->band_nm[c], tp->band_std_nm, tp->panels) / norm;
+        }
+    return 0;
+}
+
+/* LUT lookup with linear interpolation; T clamped to the LUT domain. */
+static double lut_lookup(const orc_temp_params *tp, const double *row, double T)
+{
+    int L = tp->lut_size;
+    double pos = (T - tp->t_min) / (tp->t_max - tp->t_min) * (double)(L - 1);
+    if (pos < 0.0) pos = 0.0;
+    if (pos > (double)(L - 1)) pos = (double)(L - 1);
+    int i = (int)floor(pos);
+    if (i > L - 2) i = L - 2;
+    double f = pos - (double)i;
+    return row[i] * (1.0 - f) + row[i + 1] * f;
+}
+
+/* Per key point: emission eps_c = B_c(T) from the LUT (em may be NULL) and
+ * extinction sigma = sigma_max * max(0, (T - soot_t0) / soot_span) (soot
+ * load grows with temperature). em [3][n], sig [n]. */
+void orc_temp_map(const orc_temp_params *tp, const double *lut, const double *T, long n, double *em,
+                  double *sig)
+{
+    int L = tp->lut_size;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        if (em)
+            for (int c = 0; c < 3; ++c) em[(long)c * n + i] = lut_lookup(tp, lut + (long)c * L, T[i]);
+        if (sig) {
+            double s = (T[i] - tp->soot_t0) / tp->soot_span;
+            sig[i] = tp->sigma_max * (s > 0.0 ? s : 0.0);
+        }
+    }
+}
+
+/* Inverse of the fit channel's LUT: e clamped to [B(t_min), B(t_max)], the
+ * bracketing entries found by bisection (the table is increasing), then
+ * linear interpolation between their temperatures. */
+void orc_temp_invert(const orc_temp_params *tp, const double *lut, const double *e, long n, double *T)
+{
+    int L = tp->lut_size;
+    const double *row = lut + (long)tp->channel * L;
+    double dT = (tp->t_max - tp->t_min) / (double)(L - 1);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double x = e[i];
+        if (x <= row[0]) { T[i] = tp->t_min; continue; }
+        if (x >= row[L - 1]) { T[i] = tp->t_max; continue; }
+        int lo = 0, hi = L - 1; /* row[lo] <= x < row[hi] */
+        while (hi - lo > 1) {
+            int mid = (lo + hi) / 2;
+            if (row[mid] <= x) lo = mid; else hi = mid;
+        }
+        double f = (x - row[lo]) / (row[hi] - row[lo]);
+        T[i] = tp->t_min + ((double)lo + f) * dT;
+    }
+}
+
+/* Temperature reconstruction (Sec. 3.3: reconstruct the green channel as in
+ * the colour reconstruction, then read the temperature off the
+ * colour-temperature mapping). The extinction follows the temperature
+ * (soot load), so it is re-derived from the current estimate every
+ * iteration. Per iteration:
+ *   1. eps = B_ch(T), sigma = sigma(T)                  (map)
+ *   2. I = A(sigma) eps                                 (render, fit channel)
+ *   3. q = F_ch / I on rays with I > 0, else 1          (residual ratio)
+ *   4. N = A(sigma)^T q, Cs = A(sigma)^T 1              (back-projection)
+ *   5. eps <- clamp(eps * (1 + lambda (N / Cs - 1)), B_ch(t_min), B_ch(t_max))
+ *   6. T = B_ch^{-1}(eps)                               (inverse map)
+ * The multiplicative (EM) step keeps each voxel's relative change bounded.
+ * An additive step (eps += N'/Cs with residual differences) is unstable
+ * here: near t_min the map T(eps) is so steep that round-off in eps moves
+ * T, hence sigma, by amounts whose effect on the frames grows without bound
+ * from one iteration to the next.
+ * frames [V][3][H][W] (only the fit channel is read), T_io [N]. */
+int orc_temperature_fit(const orc_grid *g, const orc_camera *cams, int32_t V, double step_vox,
+                        const orc_temp_params *tp, const double *lut, const double *frames,
+                        double *T_io, int32_t iters, double lambda, double *resid_out)
+{
+    long N = grid_nodes(g);
+    long HW = (long)cams[0].width * cams[0].height;
+    int L = tp->lut_size;
+    const double *row = lut + (long)tp->channel * L;
+    double *eps = (double *)malloc(sizeof(double) * N);
+    double *sig = (double *)malloc(sizeof(double) * N);
+    double *cols = (double *)malloc(sizeof(double) * N);
+    double *num = (double *)malloc(sizeof(double) * N);
+    double *img = (double *)malloc(sizeof(double) * V * HW);
+    double *q = (double *)malloc(sizeof(double) * V * HW);
+    double *ones_img = (double *)malloc(sizeof(double) * V * HW);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * N);
+    int rc = 0;
+    if (!eps || !sig || !cols || !num || !img || !q || !ones_img || !tmp) {
+        rc = -2;
+        goto done;
+    }
+    for (long i = 0; i < V * HW; ++i) ones_img[i] = 1.0;
+    for (int it = 0; it < iters; ++it) {
+        orc_temp_map(tp, lut, T_io, N, tmp, sig);
+        memcpy(eps, tmp + (long)tp->channel * N, sizeof(double) * N);
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, eps, sig, 0, NULL, img, NULL);
+        if (rc) goto done;
+        double r2 = 0.0;
+        for (int v = 0; v < V; ++v)
+            for (long p = 0; p < HW; ++p) {
+                double F = frames[((long)v * 3 + tp->channel) * HW + p];
+                double I = img[(long)v * HW + p];
+                r2 += (F - I) * (F - I);
+                q[(long)v * HW + p] = I > 0.0 ? F / I : 1.0;
+            }
+        if (resid_out) resid_out[it] = r2;
+        rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, q, num);
+        if (rc) goto done;
+        rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, ones_img, cols);
+        if (rc) goto done;
+        for (long j = 0; j < N; ++j) {
+            double e = eps[j];
+            if (cols[j] > 0.0) e *= 1.0 + lambda * (num[j] / cols[j] - 1.0);
+            if (e < row[0]) e = row[0];
+            if (e > row[L - 1]) e = row[L - 1];
+            eps[j] = e;
+        }
+        orc_temp_invert(tp, lut, eps, N, T_io);
+    }
+done:
+    free(eps); free(sig); free(cols); free(num); free(img); free(q); free(ones_img); free(tmp);
+    return rc;
+}
+
+int orc_num_threads(void) { return n_threads(); }
