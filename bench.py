@@ -1,0 +1,215 @@
+"""Throughput of the reconstruction hot path on one MI355X.
+
+A step is one iteration of the reconstruction loop over the whole workload
+(in-scatter grid, render of every view with the fused residual, voxel-owned
+back-projection, update). Inputs are seeded synthetic volumes and camera
+rings, resident in HBM before timing starts.
+
+  python bench.py [--steps K] [--warmup W] [--workload colour|temperature|tiny]
+
+Prints one JSON line. The metric is march samples per second (sum over all
+pixel rays of their segment counts, times iterations, over wall time).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per march sample (trilinear gathers of the render and the
+# per-corner accumulation of the back-projection; no cache filtering).
+#   render : 8 corners x (C emission + 1 extinction) x 4 B  [+ 8 x 12 B in-scatter grid]
+#   gather : 8 corners x C accumulators x 4 B
+def bytes_per_sample(C: int, scatter: bool):
+    render = 8 * (C + 1) * 4 + (8 * 12 if scatter else 0)
+    gather = 8 * C * 4
+    return render, gather
+
+
+WORKLOADS = {
+    "colour": dict(n=128, views=8, W=512, H=512, C=3, albedo=0.3, M=32, dirs=32, iters=20),
+    "temperature": dict(n=128, views=8, W=512, H=512, C=1, albedo=0.0, M=0, dirs=32, iters=30),
+    "tiny": dict(n=32, views=4, W=64, H=64, C=1, albedo=0.0, M=0, dirs=32, iters=5),
+}
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("rte_kernels.hip",):
+        h.update(open(os.path.join(ROOT, "paper_1809_06417_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or measured on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(g, rig, em, sig, frames, wl, views):
+    """The FP64 oracle (as it stands) on a bounded sample: one iteration of the
+    same loop (in-scatter grid, render, back-projection) restricted to the
+    first `views` views."""
+    import numpy as np
+
+    import oracle
+    sub = rig.subset(range(views))
+    em64, sig64 = np.asarray(em, np.float64), np.asarray(sig, np.float64)
+    F = np.asarray(frames[:views], np.float64)
+    _, _, K = oracle.ray_table(g, sub, 0.5)
+    samples = int(K.sum())
+    t0 = time.perf_counter()
+    S = None
+    if wl["albedo"] > 0:
+        S = oracle.inscatter(g, em64, sig64, s_res=wl["M"], n_dirs=wl["dirs"])
+    I, R = oracle.render(g, sub, em64, sig64, albedo=wl["albedo"], inscatter=S, rowsum=True)
+    y = np.where(R[:, None] > 0, (F - I) / np.where(R[:, None] > 0, R[:, None], 1.0), 0.0)
+    oracle.backproject_adjoint(g, sub, sig64, y)
+    dt = time.perf_counter() - t0
+    return dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"one FP64 iteration (in-scatter grid, render, back-projection) on "
+                       f"{views} of {rig.n_views} views: {samples} samples in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="colour", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
+              f"(view sharding + one all-reduce per iteration) is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1809_06417_amd import rte
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = WORKLOADS[args.workload]
+    print(f"[bench] workload {args.workload}: building inputs", file=sys.stderr, flush=True)
+    if args.workload == "colour":
+        g, em, sig = synth.colour_volume(args.seed, n=wl["n"])
+    elif args.workload == "tiny":
+        g, em, sig = synth.tiny_volume(args.seed, n=wl["n"])
+    else:
+        g, T = synth.temperature_volume(args.seed, n=wl["n"])
+    rig = synth.ring_rig(wl["views"], wl["W"], wl["H"])
+    C = wl["C"]
+    plan = rte.Plan(g, rig, channels=C, step_vox=0.5, albedo=wl["albedo"],
+                    scatter_res=wl["M"], scatter_dirs=wl["dirs"])
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+    if args.workload == "temperature":
+        tp = rte.TempParams()
+        Td = dev(T)
+        em3, sg = plan.temperature_map(Td, tp)
+        frames = torch.zeros((wl["views"], 3, wl["H"], wl["W"]), device="cuda")
+        frames[:, 1] = plan.render(em3[1:2].contiguous(), sg)[:, 0]
+        x0 = torch.full_like(Td, 800.0)
+        step_fn = lambda x, k: plan.reconstruct_temperature(frames, x, k, tp)
+    else:
+        emd, sigd = dev(em), dev(sig)
+        S = plan.inscatter(emd, sigd) if wl["albedo"] > 0 else None
+        frames = plan.render(emd, sigd, S)
+        x0 = torch.zeros_like(emd)
+        step_fn = lambda x, k: plan.reconstruct(frames, sigd, x, k)
+    torch.cuda.synchronize()
+    print(f"[bench] plan: {plan.samples} samples/iteration, {plan.hit_rays} hit rays, "
+          f"{plan.device_bytes / 2**20:.0f} MiB workspace", file=sys.stderr, flush=True)
+
+    x = x0.clone()
+    if args.warmup > 0:
+        step_fn(x, args.warmup)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    x = x0.clone()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_fn(x, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktimes = {k: plan.kernel_time(k) for k in rte.KERNELS}
+    plan.set_timing(False)
+    print(f"[bench] timed {args.steps} steps in {elapsed * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    samples = plan.samples
+    value = samples * args.steps / elapsed
+    b_render, b_gather = bytes_per_sample(C, wl["albedo"] > 0)
+    cands = {"render": b_render, "gather": b_gather}
+    per_kernel = {}
+    for k, (ms, n) in ktimes.items():
+        if n:
+            per_kernel[k] = {"avg_ms": ms / n, "launches": n, "total_ms": ms}
+    dom = max(cands, key=lambda k: ktimes[k][0])
+    dom_avg_s = ktimes[dom][0] / max(ktimes[dom][1], 1) / 1e3
+    achieved = cands[dom] * samples / dom_avg_s / 1e9
+    traffic = load_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_sample": cands[dom], "samples_per_launch": samples}
+
+    base = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
+        if args.workload == "temperature":
+            base = None
+        else:
+            base = cpu_baseline(g, rig, em, sig, frames.cpu().numpy(), wl,
+                                min(args.cpu_views, wl["views"]))
+
+    out = {
+        "metric": "ray samples/s per render+backproject iteration",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['n']}^3 grid, {C} channel(s), "
+                               f"{wl['views']} views of {wl['W']}x{wl['H']}, step 0.5 voxel, "
+                               f"albedo {wl['albedo']}" + (f", in-scatter {wl['M']}^3 x {wl['dirs']} dirs"
+                                                           if wl["M"] else ""),
+                   "samples_per_step": samples, "hit_rays": plan.hit_rays,
+                   "frames_per_s": args.steps / elapsed / wl["iters"]},
+        "roofline": roofline,
+        "cpu_baseline": base,
+        "kernels": per_kernel,
+    }
+    print(json.dumps(out))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * rte.h -- C ABI of librte, an MI355X (gfx950) implementation of the
+ * iterative loop of radiative-transport flame volume reconstruction
+ * (Shen et al., "Radiative Transport Based Flame Volume Reconstruction from
+ * Videos", arXiv:1809.06417): render every camera view of a voxel volume by
+ * perspective ray marching (Eq. 5-8, Sec. 3.3), compare with the captured
+ * frames, back-project the residuals into a volume update (Eq. 10-11,
+ * Alg. 2), and the same loop for the black-body temperature fit (Eq. 13,
+ * Sec. 3.3 "Temperature Reconstruction").
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer to FP32 (or int32 where
+ *    stated), C-contiguous, owned by the caller. The library never frees or
+ *    retains caller memory beyond the call.
+ *  - Volumes are [channel][z][y][x] (x fastest) on a node-centred grid: nx,
+ *    ny, nz key points at the voxel vertices (Sec. 3.3 "Key points")
+ *    spanning [bbox_min, bbox_max]; trilinear interpolation between them.
+ *  - Cameras: x_cam = R x_world + t; pixel (u, v) has its centre at
+ *    (u + 1/2, v + 1/2); u grows right, v down, the optical axis is +z_cam.
+ *    All cameras of a plan share one width x height.
+ *  - Images are [view][channel][v][u].
+ *  - Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream). Argument errors are detected before anything is enqueued.
+ *    Execution errors surface at the caller's next synchronisation.
+ *  - Return value: RTE_OK (0) or a negative RTE_ERR_* code; rte_last_error()
+ *    gives a message. After an argument or budget error nothing was
+ *    enqueued and in/out arrays are untouched.
+ *  - A plan may be used by one stream at a time; distinct plans are
+ *    independent. Hot calls never allocate device memory: every workspace
+ *    is allocated by rte_plan_create.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTE_OK 0
+#define RTE_ERR_INVALID_ARG (-1)
+#define RTE_ERR_BUDGET (-2)
+#define RTE_ERR_HIP (-3)
+#define RTE_ERR_UNSUPPORTED (-4)
+
+/* Pinhole camera (perspective projection, Sec. 3.2; intrinsics and
+ * extrinsics from calibration, Sec. 4.1). Double precision: the per-plan ray
+ * table is derived from it in FP64. R is row-major. */
+typedef struct {
+    double fx, fy, cx, cy;
+    double R[9];
+    double t[3];
+    int32_t width, height;
+} rte_camera;
+
+/* Node-centred grid of key points (Sec. 3.3): n >= 2 per axis. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double bbox_min[3], bbox_max[3];
+} rte_grid;
+
+/* Forward model (Eq. 5-9).
+ *  channels      1 or 3 emission channels (R, G, B reconstructed together, Sec. 3).
+ *  step_vox      sampling step along each ray in units of the smallest node
+ *                spacing (Sec. 4.2 uses one voxel; 0.5 is the default here).
+ *  albedo        sigma_s / sigma_t; 0 disables in-scattering.
+ *  background    radiance behind the volume (0: dark capture, Sec. 4.1).
+ *  scatter_res   nodes per axis of the in-scatter grid (>= 2 when albedo > 0).
+ *  scatter_dirs  directions of the isotropic in-scatter average (1..256).
+ *  scatter_step  in-scatter march step in units of the in-scatter node spacing. */
+typedef struct {
+    int32_t channels;
+    float step_vox;
+    float albedo;
+    float background;
+    int32_t scatter_res;
+    int32_t scatter_dirs;
+    float scatter_step;
+} rte_render_params;
+
+/* Back-projection weights. */
+typedef enum {
+    RTE_BP_ADJOINT = 0, /* exact transpose of the linear emission -> image map */
+    RTE_BP_PAPER = 1    /* adjustment values of Eq. 10 with the transparency of Eq. 12 */
+} rte_bp_mode;
+
+/* Volume update rule of the reconstruction loop. */
+typedef enum {
+    RTE_UPDATE_SART = 0,  /* e += lambda * (A^T 1)^-1 A^T (A 1)^-1 (F - I), all views at once */
+    RTE_UPDATE_PAPER = 1, /* e += sum_s A_js (Eq. 10-11 with G = 1) */
+    RTE_UPDATE_MLEM = 2   /* e *= 1 + lambda * (A^T (F / I) / A^T 1 - 1) */
+} rte_update;
+
+/* Reconstruction parameters.
+ *  update        an rte_update value.
+ *  lambda        relaxation (SART, MLEM); 1 is the plain step.
+ *  clamp_nonneg  clamp the emission at 0 after each update (SART, PAPER).
+ *  alpha_l, alpha_d, tau   paper-mode constants of Eq. 10 and Eq. 12
+ *                (Sec. 5.1 uses 0.001, 1, 0.05; D is measured in voxels). */
+typedef struct {
+    int32_t update;
+    float lambda;
+    int32_t clamp_nonneg;
+    float alpha_l, alpha_d, tau;
+} rte_recon_params;
+
+/* Colour-temperature mapping (Eq. 13; Sec. 3.3). The LUT holds, at lut_size
+ * temperatures evenly spaced over [t_min, t_max], the band radiances
+ *   B_c(T) = int B(lambda, T) w_c(lambda) dlambda / int B(lambda, t_norm) w_ch(lambda) dlambda,
+ * w_c a Gaussian band of centre band_nm[c] and standard deviation
+ * band_std_nm, integrated by composite Simpson with `panels` panels over
+ * +-6 standard deviations (built on the host in FP64). Extinction follows
+ * the soot load: sigma = sigma_max * max(0, (T - soot_t0) / soot_span).
+ * `channel` is the fitted channel (1 = green, Sec. 3.3). */
+typedef struct {
+    float t_min, t_max, t_norm;
+    float band_nm[3];
+    float band_std_nm;
+    int32_t lut_size;
+    float sigma_max, soot_t0, soot_span;
+    int32_t channel;
+    int32_t panels;
+} rte_temp_params;
+
+typedef struct rte_plan rte_plan;
+
+/* Build a plan for one grid and camera rig (host structs). Computes the ray
+ * table on the device (per pixel: entry point, chord length and segment
+ * count; Alg. 2 casts one ray per pixel) and allocates every workspace.
+ * Synchronises `stream` once. Fails with RTE_ERR_BUDGET, allocating
+ * nothing that it keeps, if the workspace would exceed hbm_budget_bytes
+ * (0 = no limit). *out receives the plan. */
+int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                    const rte_render_params *params, size_t hbm_budget_bytes, void *stream);
+
+/* Upper bound of the device bytes rte_plan_create would allocate for these
+ * arguments (host-side estimate; no device work). Returns 0 on invalid
+ * arguments. */
+size_t rte_plan_workspace_bytes(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                                const rte_render_params *params);
+
+/* Device bytes actually held by the plan. */
+size_t rte_plan_device_bytes(const rte_plan *plan);
+
+/* Release the plan (synchronises its last stream first). NULL is ignored. */
+void rte_plan_destroy(rte_plan *plan);
+
+/* Number of march samples of one pass over all rays (sum of the segment
+ * counts) and number of rays that hit the volume. */
+int rte_plan_counts(const rte_plan *plan, uint64_t *samples, uint64_t *hit_rays);
+
+/* Export the ray table: t_near, t_far (world units along the unit ray
+ * direction) and segment count K per pixel, [view][v][u] device arrays.
+ * Rays that miss get K = 0 and t_near = t_far = 0. */
+int rte_ray_table(rte_plan *plan, float *t_near, float *t_far, int32_t *nseg, void *stream);
+
+/* Render every view (Eq. 5-8 along each ray, front to back):
+ *   I_c = sum_k T_k j_kc Delta_k phi(sigma_k Delta_k) + T_K * background,
+ *   T_{k+1} = T_k exp(-sigma_k Delta_k),  phi(x) = (1 - e^-x) / x,
+ *   j_kc = eps_c(x_k) + albedo * sigma(x_k) * S_c(x_k),
+ * with segment midpoints x_k, the last segment clipped at the exit.
+ * emission [C][nz][ny][nx], extinction [nz][ny][nx] (>= 0),
+ * inscatter [C][M][M][M] (M = scatter_res) or NULL (no in-scattering),
+ * images [V][C][H][W] (written). */
+int rte_render(rte_plan *plan, const float *emission, const float *extinction,
+               const float *inscatter, float *images, void *stream);
+
+/* In-scattered radiance grid (Eq. 5 third term, isotropic phase function of
+ * Eq. 9 at g = 0): at each node p of an M^3 grid over the box, the mean over
+ * scatter_dirs spherical-Fibonacci directions u of the emission-absorption
+ * march from p along u to the box exit (single scattering).
+ * emission [C][nz][ny][nx], extinction [nz][ny][nx], inscatter [C][M][M][M]
+ * (written). */
+int rte_inscatter(rte_plan *plan, const float *emission, const float *extinction, float *inscatter,
+                  void *stream);
+
+/* Back-project per-pixel values into a per-key-point volume (Alg. 2
+ * adjustment pass, computed as an atomics-free voxel-owned gather).
+ *  RTE_BP_ADJOINT: delta = A^T residual, A the linear emission -> image map
+ *    of rte_render at this extinction without in-scattering or background.
+ *  RTE_BP_PAPER: delta_j = sum over samples s touching j of
+ *    alpha_l * residual * (1 - tau)^k * exp(-alpha_d * D(j, s))   (Eq. 10, 12;
+ *    k = 0-based sample order from the ray's entry, D in voxels); `params`
+ *    supplies alpha_l, alpha_d, tau and may be NULL for ADJOINT.
+ * extinction [nz][ny][nx] (ADJOINT only; may be NULL for PAPER),
+ * residual [V][C][H][W], delta [C][nz][ny][nx] (written). */
+int rte_backproject(rte_plan *plan, const float *extinction, const float *residual, float *delta,
+                    int32_t mode, const rte_recon_params *params, void *stream);
+
+/* Iterative colour reconstruction (Sec. 3: render, compare with the frames,
+ * adjust the volume; repeated `iters` times). The extinction is known and
+ * fixed; in-scattering (albedo > 0) is recomputed from the current emission
+ * at the start of every iteration and held fixed within it. Row and column
+ * sums of A are computed once per call.
+ * frames [V][C][H][W], extinction [nz][ny][nx], emission [C][nz][ny][nx]
+ * (in: start volume, out: result; warm start = pass the previous result). */
+int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction, float *emission,
+                    int32_t iters, const rte_recon_params *params, void *stream);
+
+/* Temperature fit (Sec. 3.3): per iteration, map T -> (eps_ch, sigma) through
+ * the LUT, render the fitted channel, back-project the frame/render ratio
+ * (multiplicative EM step; params->update is ignored), clamp eps_ch to the
+ * LUT range and invert the LUT to get T. The plan must have channels = 1.
+ * frames [V][3][H][W] (only temp->channel is read), temperature
+ * [nz][ny][nx] in Kelvin (in: start, out: result). */
+int rte_reconstruct_temperature(rte_plan *plan, const float *frames, float *temperature,
+                                int32_t iters, const rte_recon_params *params,
+                                const rte_temp_params *temp, void *stream);
+
+/* Colour-temperature map alone: emission [3][nz][ny][nx] = B_c(T) (may be
+ * NULL) and extinction [nz][ny][nx] = sigma(T) (may be NULL) from
+ * temperature [nz][ny][nx]. */
+int rte_temperature_map(rte_plan *plan, const float *temperature, float *emission,
+                        float *extinction, const rte_temp_params *temp, void *stream);
+
+/* Inverse of the fitted channel's map: temperature = B_ch^-1(clamp(e)) by
+ * bisection of the LUT and linear interpolation; e [nz][ny][nx]. */
+int rte_temperature_invert(rte_plan *plan, const float *e, float *temperature,
+                           const rte_temp_params *temp, void *stream);
+
+/* Copy of the FP32 LUT the device uses, [3][lut_size] host array (for
+ * inspection); lut_size must equal temp->lut_size. Synchronous. */
+int rte_temperature_lut(rte_plan *plan, const rte_temp_params *temp, float *lut_host,
+                        int32_t lut_size);
+
+/* Per-kernel timing: when enabled, every launch of the plan is bracketed by
+ * HIP events on the launch stream. rte_plan_kernel_time synchronises on the
+ * recorded events and returns the total milliseconds and launch count of
+ * kernel `kernel` (RTE_KERNEL_* below) since the last reset. */
+enum {
+    RTE_KERNEL_RAYS = 0,
+    RTE_KERNEL_RENDER = 1,
+    RTE_KERNEL_INSCATTER = 2,
+    RTE_KERNEL_GATHER = 3,
+    RTE_KERNEL_UPDATE = 4,
+    RTE_KERNEL_TEMP_MAP = 5,
+    RTE_KERNEL_PACK = 6,
+    RTE_KERNEL_COUNT = 7
+};
+int rte_plan_set_timing(rte_plan *plan, int32_t enable);
+int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char *rte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

@@ -1,0 +1,703 @@
+// C ABI of librte: plan construction, argument validation, workspace and
+// HBM budget, kernel sequencing on the caller's stream, per-kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rte_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return RTE_OK;
+}
+
+#define RTE_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(RTE_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr int kMaxLut = 65536;
+constexpr int kMaxDirs = 256;
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Validate grid / cameras / params; fills the derived sizes of a plan.
+int validate_config(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                    const rte_render_params *params)
+{
+    if (!grid || !cams || !params) return fail(RTE_ERR_INVALID_ARG, "null grid, cameras or params");
+    if (grid->nx < 2 || grid->ny < 2 || grid->nz < 2)
+        return fail(RTE_ERR_INVALID_ARG, "grid needs at least 2 key points per axis (got %d %d %d)",
+                    grid->nx, grid->ny, grid->nz);
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(grid->bbox_min[i]) || !std::isfinite(grid->bbox_max[i]) ||
+            !(grid->bbox_max[i] > grid->bbox_min[i]))
+            return fail(RTE_ERR_INVALID_ARG, "bbox axis %d is empty or not finite", i);
+    const int64_t nodes = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (nodes >= (int64_t(1) << 31) / 4)
+        return fail(RTE_ERR_INVALID_ARG, "grid too large (%lld key points)", (long long)nodes);
+    if (ncams < 1) return fail(RTE_ERR_INVALID_ARG, "need at least one camera");
+    const int W = cams[0].width, H = cams[0].height;
+    if (W < 1 || H < 1) return fail(RTE_ERR_INVALID_ARG, "camera 0 has an empty image");
+    for (int v = 0; v < ncams; ++v) {
+        const rte_camera &c = cams[v];
+        if (c.width != W || c.height != H)
+            return fail(RTE_ERR_INVALID_ARG, "camera %d image size differs from camera 0", v);
+        if (!std::isfinite(c.fx) || !std::isfinite(c.fy) || c.fx == 0.0 || c.fy == 0.0 ||
+            !std::isfinite(c.cx) || !std::isfinite(c.cy))
+            return fail(RTE_ERR_INVALID_ARG, "camera %d has invalid intrinsics", v);
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(c.R[i])) return fail(RTE_ERR_INVALID_ARG, "camera %d: R not finite", v);
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(c.t[i])) return fail(RTE_ERR_INVALID_ARG, "camera %d: t not finite", v);
+    }
+    const int C = params->channels;
+    if (C != 1 && C != 3) return fail(RTE_ERR_INVALID_ARG, "channels must be 1 or 3 (got %d)", C);
+    if ((int64_t)ncams * W * H * C >= (int64_t(1) << 31))
+        return fail(RTE_ERR_INVALID_ARG, "images too large for 32-bit indexing");
+    if (!finite_pos(params->step_vox)) return fail(RTE_ERR_INVALID_ARG, "step_vox must be > 0");
+    if (!std::isfinite(params->albedo) || params->albedo < 0.0f)
+        return fail(RTE_ERR_INVALID_ARG, "albedo must be >= 0");
+    if (!std::isfinite(params->background))
+        return fail(RTE_ERR_INVALID_ARG, "background must be finite");
+    if (params->albedo > 0.0f || params->scatter_res != 0) {
+        if (params->scatter_res < 2 || params->scatter_res > 1024)
+            return fail(RTE_ERR_INVALID_ARG, "scatter_res must be in [2, 1024] with albedo > 0");
+        if (params->scatter_dirs < 1 || params->scatter_dirs > kMaxDirs)
+            return fail(RTE_ERR_INVALID_ARG, "scatter_dirs must be in [1, %d]", kMaxDirs);
+        if (!finite_pos(params->scatter_step))
+            return fail(RTE_ERR_INVALID_ARG, "scatter_step must be > 0");
+    }
+    return RTE_OK;
+}
+
+struct Derived {
+    int V, W, H, tiles_x, tiles_y, tiles_per_view, n_tiles;
+    int64_t n_rays, n_nodes, n_cells;
+    double h[3], ds;
+};
+
+Derived derive(const rte_grid *grid, const rte_camera *cams, int32_t ncams, const rte_render_params *params)
+{
+    Derived d{};
+    d.V = ncams;
+    d.W = cams[0].width;
+    d.H = cams[0].height;
+    d.tiles_x = (d.W + rte::kTile - 1) / rte::kTile;
+    d.tiles_y = (d.H + rte::kTile - 1) / rte::kTile;
+    d.tiles_per_view = d.tiles_x * d.tiles_y;
+    d.n_tiles = d.tiles_per_view * d.V;
+    d.n_rays = (int64_t)d.V * d.W * d.H;
+    d.n_nodes = (int64_t)grid->nx * grid->ny * grid->nz;
+    d.n_cells = (int64_t)(grid->nx - 1) * (grid->ny - 1) * (grid->nz - 1);
+    const int n[3] = {grid->nx, grid->ny, grid->nz};
+    double hmin = 1e300;
+    for (int i = 0; i < 3; ++i) {
+        d.h[i] = (grid->bbox_max[i] - grid->bbox_min[i]) / (double)(n[i] - 1);
+        hmin = std::min(hmin, d.h[i]);
+    }
+    d.ds = (double)params->step_vox * hmin;
+    return d;
+}
+
+// Host estimate of the per-tile maximum segment count (same FP64 geometry as
+// the device ray table), used for the workspace bound before any device work.
+std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, const Derived &d)
+{
+    std::vector<int> kmax(d.n_tiles, 0);
+    for (int v = 0; v < d.V; ++v) {
+        const rte_camera &c = cams[v];
+        double o[3];
+        for (int i = 0; i < 3; ++i) o[i] = -(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] + c.R[2 * 3 + i] * c.t[2]);
+        for (int py = 0; py < d.H; ++py)
+            for (int px = 0; px < d.W; ++px) {
+                const double dc0 = ((double)px + 0.5 - c.cx) / c.fx, dc1 = ((double)py + 0.5 - c.cy) / c.fy;
+                double dir[3], n2 = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    dir[i] = c.R[0 * 3 + i] * dc0 + c.R[1 * 3 + i] * dc1 + c.R[2 * 3 + i];
+                    n2 += dir[i] * dir[i];
+                }
+                const double inv = 1.0 / std::sqrt(n2);
+                double t0 = -INFINITY, t1 = INFINITY;
+                bool hit = true;
+                for (int i = 0; i < 3; ++i) {
+                    const double di = dir[i] * inv;
+                    if (di != 0.0) {
+                        double ta = (grid->bbox_min[i] - o[i]) / di, tb = (grid->bbox_max[i] - o[i]) / di;
+                        if (ta > tb) std::swap(ta, tb);
+                        t0 = std::max(t0, ta);
+                        t1 = std::min(t1, tb);
+                    } else if (o[i] < grid->bbox_min[i] || o[i] > grid->bbox_max[i]) {
+                        hit = false;
+                    }
+                }
+                t0 = std::max(t0, 0.0);
+                if (!hit || !(t1 > t0)) continue;
+                const int K = (int)std::ceil((t1 - t0) / d.ds);
+                int &m = kmax[(size_t)v * d.tiles_per_view + (py / rte::kTile) * d.tiles_x + px / rte::kTile];
+                m = std::max(m, K);
+            }
+    }
+    return kmax;
+}
+
+struct Sizes {
+    size_t cams, proj, rays, tnear, tiles, g, vol, scat, dirs, y, part, cols, lut, total;
+    int part_acc, lut_cap;
+};
+
+Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_floats)
+{
+    Sizes s{};
+    const int C = params->channels;
+    const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
+    s.part_acc = std::max(C, 2);
+    s.lut_cap = kMaxLut;
+    s.cams = sizeof(rte_camera) * d.V;
+    s.proj = sizeof(rte::ViewProj) * d.V;
+    s.rays = 2 * sizeof(float4) * d.n_rays;
+    s.tnear = sizeof(float) * d.n_rays;
+    s.tiles = (sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
+    s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
+    s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
+    s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
+    s.dirs = sizeof(float4) * kMaxDirs;
+    s.y = sizeof(float) * (size_t)d.n_rays * C;
+    s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_cells, 1);
+    s.cols = sizeof(float) * d.n_nodes;
+    s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
+    s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.vol + s.scat + s.dirs + s.y +
+              s.part + s.cols + s.lut;
+    return s;
+}
+
+// ------------------------------------------------------------------ timing
+
+hipEvent_t take_event(rte_plan *p);
+
+void drain_timing(rte_plan *p)
+{
+    for (auto &r : p->pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            p->kernel_ms[r.kernel] += ms;
+            p->kernel_launches[r.kernel] += 1;
+        }
+        p->event_pool.push_back(r.start);
+        p->event_pool.push_back(r.stop);
+    }
+    p->pending.clear();
+}
+
+hipEvent_t take_event(rte_plan *p)
+{
+    if (p->event_pool.empty()) drain_timing(p);
+    if (p->event_pool.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct Timed {
+    rte_plan *p;
+    int kernel;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr;
+    Timed(rte_plan *p_, int k, hipStream_t s_) : p(p_), kernel(k), s(s_)
+    {
+        if (p->timing) {
+            e0 = take_event(p);
+            if (e0) hipEventRecord(e0, s);
+        }
+    }
+    hipError_t done(hipError_t launch_status)
+    {
+        if (p->timing && e0) {
+            hipEvent_t e1 = take_event(p);
+            if (e1) {
+                hipEventRecord(e1, s);
+                p->pending.push_back({kernel, e0, e1});
+            }
+        }
+        return launch_status;
+    }
+};
+
+#define RTE_LAUNCH(plan, kid, stream, call)                                               \
+    do {                                                                                  \
+        Timed t_((plan), (kid), (stream));                                                \
+        hipError_t e_ = t_.done(call);                                                    \
+        if (e_ != hipSuccess)                                                             \
+            return fail(RTE_ERR_HIP, "launch of %s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+int dev_alloc(T **ptr, size_t bytes, size_t &acc)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(RTE_ERR_HIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    *ptr = static_cast<T *>(p);
+    acc += bytes;
+    return RTE_OK;
+}
+
+void free_plan(rte_plan *p)
+{
+    if (!p) return;
+    hipDeviceSynchronize();
+    for (auto &r : p->pending) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    for (auto e : p->event_pool) hipEventDestroy(e);
+    void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
+                    p->d_tile_off, p->d_g, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
+                    p->d_cols, p->d_lut};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    delete p;
+}
+
+// Voxel-coordinate -> homogeneous pixel projection of each view.
+rte::ViewProj view_projection(const rte_grid *g, const rte_camera &c, const double h[3])
+{
+    // x_w = lo + h * X ; x_c = R x_w + t ; (hu, hv, hw) = (fx xc + cx zc, fy yc + cy zc, zc)
+    double Rh[3][4];
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) Rh[r][k] = c.R[r * 3 + k] * h[k];
+        Rh[r][3] = c.R[r * 3 + 0] * g->bbox_min[0] + c.R[r * 3 + 1] * g->bbox_min[1] +
+                   c.R[r * 3 + 2] * g->bbox_min[2] + c.t[r];
+    }
+    rte::ViewProj vp{};
+    for (int k = 0; k < 4; ++k) {
+        vp.P[0 + k] = (float)(c.fx * Rh[0][k] + c.cx * Rh[2][k]);
+        vp.P[4 + k] = (float)(c.fy * Rh[1][k] + c.cy * Rh[2][k]);
+        vp.P[8 + k] = (float)Rh[2][k];
+    }
+    return vp;
+}
+
+int check_plan(const rte_plan *p)
+{
+    if (!p) return fail(RTE_ERR_INVALID_ARG, "null plan");
+    return RTE_OK;
+}
+
+int ensure_lut(rte_plan *p, const rte_temp_params *tp, hipStream_t s)
+{
+    if (!tp) return fail(RTE_ERR_INVALID_ARG, "null temperature params");
+    if (tp->lut_size < 2 || tp->lut_size > p->lut_cap)
+        return fail(RTE_ERR_INVALID_ARG, "lut_size must be in [2, %d]", p->lut_cap);
+    if (!(tp->t_max > tp->t_min) || !(tp->t_min > 0.0f) || !std::isfinite(tp->t_max) || !(tp->t_norm > 0.0f))
+        return fail(RTE_ERR_INVALID_ARG, "temperature range invalid");
+    if (!finite_pos(tp->band_std_nm)) return fail(RTE_ERR_INVALID_ARG, "band_std_nm must be > 0");
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(tp->band_nm[c]) || tp->band_nm[c] - 6.0f * tp->band_std_nm <= 0.0f)
+            return fail(RTE_ERR_INVALID_ARG, "band %d must lie at positive wavelengths", c);
+    if (tp->channel < 0 || tp->channel > 2) return fail(RTE_ERR_INVALID_ARG, "channel must be 0, 1 or 2");
+    if (!(tp->soot_span > 0.0f) || !std::isfinite(tp->sigma_max) || tp->sigma_max < 0.0f)
+        return fail(RTE_ERR_INVALID_ARG, "soot_span must be > 0 and sigma_max >= 0");
+    if (tp->panels < 2 || tp->panels > (1 << 20)) return fail(RTE_ERR_INVALID_ARG, "panels out of range");
+    if (p->lut_valid && std::memcmp(&p->lut_params, tp, sizeof(*tp)) == 0) return RTE_OK;
+    rte::build_temperature_lut(*tp, p->lut_host);
+    for (int i = 1; i < tp->lut_size; ++i)
+        if (!(p->lut_host[(size_t)tp->channel * tp->lut_size + i] >
+              p->lut_host[(size_t)tp->channel * tp->lut_size + i - 1]))
+            return fail(RTE_ERR_INVALID_ARG, "fitted channel is not increasing in temperature on [t_min, t_max]");
+    for (int c = 0; c < 3; ++c)
+        RTE_HIP(hipMemcpyAsync(p->d_lut + (size_t)c * p->lut_cap, p->lut_host.data() + (size_t)c * tp->lut_size,
+                               sizeof(float) * tp->lut_size, hipMemcpyHostToDevice, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    p->lut_params = *tp;
+    p->lut_valid = true;
+    return RTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rte_last_error(void) { return g_last_error.c_str(); }
+
+size_t rte_plan_workspace_bytes(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                                const rte_render_params *params)
+{
+    if (validate_config(grid, cams, ncams, params) != RTE_OK) return 0;
+    const Derived d = derive(grid, cams, ncams, params);
+    const std::vector<int> kmax = host_tile_kmax(grid, cams, d);
+    uint64_t g = 0;
+    for (int k : kmax) g += (uint64_t)(k + 1) * rte::kTileRays;
+    return workspace(params, d, g).total;
+}
+
+int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                    const rte_render_params *params, size_t hbm_budget_bytes, void *stream)
+{
+    if (!out) return fail(RTE_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int rc = validate_config(grid, cams, ncams, params);
+    if (rc) return rc;
+    const Derived d = derive(grid, cams, ncams, params);
+    const std::vector<int> host_kmax = host_tile_kmax(grid, cams, d);
+    uint64_t g_bound = 0;
+    for (int k : host_kmax) g_bound += (uint64_t)(k + 1) * rte::kTileRays;
+    const Sizes bound = workspace(params, d, g_bound);
+    if (hbm_budget_bytes && bound.total > hbm_budget_bytes)
+        return fail(RTE_ERR_BUDGET, "plan needs up to %zu bytes, budget is %zu", bound.total, hbm_budget_bytes);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rte_plan *p = new rte_plan();
+    p->grid = *grid;
+    p->params = *params;
+    p->cams.assign(cams, cams + ncams);
+    p->V = d.V;
+    p->W = d.W;
+    p->H = d.H;
+    p->tiles_x = d.tiles_x;
+    p->tiles_y = d.tiles_y;
+    p->tiles_per_view = d.tiles_per_view;
+    p->n_tiles = d.n_tiles;
+    p->n_rays = d.n_rays;
+    p->n_nodes = d.n_nodes;
+    p->n_cells = d.n_cells;
+    for (int i = 0; i < 3; ++i) p->h[i] = d.h[i];
+    p->ds = d.ds;
+    p->last_stream = s;
+    auto bail = [&](int code) {
+        std::string msg = g_last_error;
+        free_plan(p);
+        g_last_error = msg;
+        return code;
+    };
+
+    // ray table (K4) and per-tile maxima
+    size_t acc = 0;
+    const Sizes sz = workspace(params, d, 0);
+    if ((rc = dev_alloc(&p->d_cams, sz.cams, acc)) || (rc = dev_alloc(&p->d_proj, sz.proj, acc)) ||
+        (rc = dev_alloc(&p->d_rayA, sz.rays / 2, acc)) || (rc = dev_alloc(&p->d_rayB, sz.rays / 2, acc)) ||
+        (rc = dev_alloc(&p->d_tnear, sz.tnear, acc)) ||
+        (rc = dev_alloc(&p->d_tile_kmax, sizeof(int32_t) * d.n_tiles, acc)) ||
+        (rc = dev_alloc(&p->d_tile_off, sizeof(uint64_t) * d.n_tiles, acc)))
+        return bail(rc);
+    std::vector<rte::ViewProj> proj(d.V);
+    for (int v = 0; v < d.V; ++v) proj[v] = view_projection(grid, cams[v], d.h);
+    if (hipMemcpyAsync(p->d_cams, cams, sz.cams, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(p->d_proj, proj.data(), sz.proj, hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(RTE_ERR_HIP, "camera upload failed"));
+    {
+        Timed t(p, RTE_KERNEL_RAYS, s);
+        hipError_t e = t.done(rte::launch_ray_table(p, s));
+        if (e == hipSuccess) e = rte::launch_tile_kmax(p, s);
+        if (e != hipSuccess) return bail(fail(RTE_ERR_HIP, "ray table launch failed: %s", hipGetErrorString(e)));
+    }
+    std::vector<int32_t> kmax(d.n_tiles);
+    if (hipMemcpyAsync(kmax.data(), p->d_tile_kmax, sizeof(int32_t) * d.n_tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(RTE_ERR_HIP, "ray table readback failed"));
+    std::vector<uint64_t> off(d.n_tiles);
+    uint64_t g = 0;
+    for (int t = 0; t < d.n_tiles; ++t) {
+        if (kmax[t] > host_kmax[t] + 1)
+            return bail(fail(RTE_ERR_HIP, "device ray table disagrees with the host bound at tile %d", t));
+        off[t] = g;
+        g += (uint64_t)kmax[t] * rte::kTileRays;
+    }
+    p->g_floats = g;
+    if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint64_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess)
+        return bail(fail(RTE_ERR_HIP, "tile offsets upload failed"));
+
+    // remaining workspaces
+    const Sizes full = workspace(params, d, g);
+    const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
+    p->part_acc = full.part_acc;
+    p->lut_cap = full.lut_cap;
+    if ((rc = dev_alloc(&p->d_g, full.g, acc)) || (rc = dev_alloc(&p->d_vol, full.vol, acc)) ||
+        (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
+        (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
+        (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)))
+        return bail(rc);
+    // in-scatter directions: spherical Fibonacci, voxel units per world unit
+    if (M) {
+        std::vector<float4> dirs(kMaxDirs, make_float4(0.f, 0.f, 0.f, 0.f));
+        const int nd = params->scatter_dirs;
+        for (int k = 0; k < nd; ++k) {
+            const double z = 1.0 - (2.0 * k + 1.0) / (double)nd;
+            const double r = std::sqrt(std::max(0.0, 1.0 - z * z));
+            const double ph = (double)k * M_PI * (3.0 - std::sqrt(5.0));
+            dirs[k] = make_float4((float)(r * std::cos(ph) / d.h[0]), (float)(r * std::sin(ph) / d.h[1]),
+                                  (float)(z / d.h[2]), 0.f);
+        }
+        if (hipMemcpyAsync(p->d_dirs, dirs.data(), full.dirs, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemsetAsync(p->d_scat, 0, full.scat, s) != hipSuccess)
+            return bail(fail(RTE_ERR_HIP, "in-scatter setup failed"));
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(RTE_ERR_HIP, "plan setup sync failed"));
+    uint64_t samples = 0, hits = 0;
+    {
+        // exact counts from the device ray table
+        std::vector<float4> B(d.n_rays);
+        if (hipMemcpy(B.data(), p->d_rayB, sizeof(float4) * d.n_rays, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(RTE_ERR_HIP, "ray table count readback failed"));
+        for (const float4 &b : B) {
+            int K;
+            std::memcpy(&K, &b.w, sizeof(int));
+            samples += (uint64_t)K;
+            hits += K > 0;
+        }
+    }
+    p->samples = samples;
+    p->hit_rays = hits;
+    p->device_bytes = acc;
+    *out = p;
+    return ok();
+}
+
+size_t rte_plan_device_bytes(const rte_plan *plan) { return plan ? plan->device_bytes : 0; }
+
+void rte_plan_destroy(rte_plan *plan) { free_plan(plan); }
+
+int rte_plan_counts(const rte_plan *plan, uint64_t *samples, uint64_t *hit_rays)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (samples) *samples = plan->samples;
+    if (hit_rays) *hit_rays = plan->hit_rays;
+    return ok();
+}
+
+int rte_ray_table(rte_plan *plan, float *t_near, float *t_far, int32_t *nseg, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!t_near && !t_far && !nseg) return fail(RTE_ERR_INVALID_ARG, "no output requested");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    RTE_LAUNCH(plan, RTE_KERNEL_RAYS, s, rte::launch_ray_export(plan, t_near, t_far, nseg, s));
+    return ok();
+}
+
+int rte_render(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
+               float *images, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!emission || !extinction || !images) return fail(RTE_ERR_INVALID_ARG, "null emission, extinction or images");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    const bool scat = inscatter && plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+               rte::launch_render(plan, C, true, scat, false, rte::kEpiImage, nullptr, C, 0, images, s));
+    return ok();
+}
+
+int rte_inscatter(rte_plan *plan, const float *emission, const float *extinction, float *inscatter, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!emission || !extinction || !inscatter) return fail(RTE_ERR_INVALID_ARG, "null emission, extinction or output");
+    if (plan->params.scatter_res < 2)
+        return fail(RTE_ERR_UNSUPPORTED, "plan was created without an in-scatter grid (scatter_res < 2)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, inscatter, s));
+    return ok();
+}
+
+int rte_backproject(rte_plan *plan, const float *extinction, const float *residual, float *delta,
+                    int32_t mode, const rte_recon_params *params, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!residual || !delta) return fail(RTE_ERR_INVALID_ARG, "null residual or delta");
+    if (mode != RTE_BP_ADJOINT && mode != RTE_BP_PAPER) return fail(RTE_ERR_INVALID_ARG, "unknown back-projection mode %d", mode);
+    if (mode == RTE_BP_ADJOINT && !extinction) return fail(RTE_ERR_INVALID_ARG, "adjoint back-projection needs the extinction");
+    if (mode == RTE_BP_PAPER && !params) return fail(RTE_ERR_INVALID_ARG, "paper back-projection needs alpha_l, alpha_d, tau");
+    if (mode == RTE_BP_PAPER && !(params->tau >= 0.0f && params->tau < 1.0f))
+        return fail(RTE_ERR_INVALID_ARG, "tau must be in [0, 1)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    if (mode == RTE_BP_ADJOINT) {
+        RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, nullptr, extinction, C, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+                   rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(plan, C, rte::kGatherAdjoint, residual, 0.f, 0.f, 0.f, s));
+    } else {
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(plan, C, rte::kGatherPaper, residual, params->alpha_l,
+                                      params->alpha_d, params->tau, s));
+    }
+    RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+               rte::launch_update(plan, C, C, rte::kUpdDelta, 0.f, 0, delta, nullptr, 0, 0, s));
+    return ok();
+}
+
+int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction, float *emission,
+                    int32_t iters, const rte_recon_params *params, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!frames || !extinction || !emission || !params)
+        return fail(RTE_ERR_INVALID_ARG, "null frames, extinction, emission or params");
+    if (iters < 0) return fail(RTE_ERR_INVALID_ARG, "iters must be >= 0");
+    const int upd = params->update;
+    if (upd != RTE_UPDATE_SART && upd != RTE_UPDATE_PAPER && upd != RTE_UPDATE_MLEM)
+        return fail(RTE_ERR_INVALID_ARG, "unknown update rule %d", upd);
+    if (!std::isfinite(params->lambda)) return fail(RTE_ERR_INVALID_ARG, "lambda must be finite");
+    if (upd == RTE_UPDATE_PAPER && !(params->tau >= 0.0f && params->tau < 1.0f))
+        return fail(RTE_ERR_INVALID_ARG, "tau must be in [0, 1)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    const bool scat = plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    if (upd != RTE_UPDATE_PAPER && iters > 0) {
+        // row sums come out of every render; column sums A^T 1 once per call
+        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+                   rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
+    }
+    const int epi = upd == RTE_UPDATE_SART ? rte::kEpiSart : (upd == RTE_UPDATE_MLEM ? rte::kEpiMlem : rte::kEpiPaper);
+    const int gmode = upd == RTE_UPDATE_PAPER ? rte::kGatherPaper : rte::kGatherAdjoint;
+    const int umode = upd == RTE_UPDATE_SART ? rte::kUpdSart : (upd == RTE_UPDATE_MLEM ? rte::kUpdMlem : rte::kUpdPaper);
+    for (int it = 0; it < iters; ++it) {
+        if (scat) RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, nullptr, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+                   rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_update(plan, C, C, umode, params->lambda, params->clamp_nonneg, nullptr,
+                                      nullptr, 0, 0, s));
+    }
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_unpack(plan, emission, C, s));
+    return ok();
+}
+
+int rte_reconstruct_temperature(rte_plan *plan, const float *frames, float *temperature, int32_t iters,
+                                const rte_recon_params *params, const rte_temp_params *temp, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!frames || !temperature || !params || !temp)
+        return fail(RTE_ERR_INVALID_ARG, "null frames, temperature or params");
+    if (plan->params.channels != 1) return fail(RTE_ERR_INVALID_ARG, "temperature fit needs a plan with channels = 1");
+    if (iters < 0) return fail(RTE_ERR_INVALID_ARG, "iters must be >= 0");
+    if (!std::isfinite(params->lambda)) return fail(RTE_ERR_INVALID_ARG, "lambda must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    if (int rc = ensure_lut(plan, temp, s)) return rc;
+    const rte_temp_params &tp = *temp;
+    for (int it = 0; it < iters; ++it) {
+        RTE_LAUNCH(plan, RTE_KERNEL_TEMP_MAP, s,
+                   rte::launch_temp_map(plan, temperature, nullptr, nullptr, true, tp.lut_size, tp.channel,
+                                        tp.sigma_max, tp.soot_t0, tp.soot_span, tp.t_min, tp.t_max, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+                   rte::launch_render(plan, 1, true, false, true, rte::kEpiMlem, frames, 3, tp.channel, plan->d_y, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(plan, 1, rte::kGatherAdjointCols, plan->d_y, 0.f, 0.f, 0.f, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_update(plan, 1, 2, rte::kUpdTemp, params->lambda, 0, nullptr, temperature,
+                                      tp.lut_size, tp.channel, s));
+    }
+    return ok();
+}
+
+int rte_temperature_map(rte_plan *plan, const float *temperature, float *emission, float *extinction,
+                        const rte_temp_params *temp, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!temperature || (!emission && !extinction)) return fail(RTE_ERR_INVALID_ARG, "null temperature or no output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    if (int rc = ensure_lut(plan, temp, s)) return rc;
+    RTE_LAUNCH(plan, RTE_KERNEL_TEMP_MAP, s,
+               rte::launch_temp_map(plan, temperature, emission, extinction, false, temp->lut_size, temp->channel,
+                                    temp->sigma_max, temp->soot_t0, temp->soot_span, temp->t_min, temp->t_max, s));
+    return ok();
+}
+
+int rte_temperature_invert(rte_plan *plan, const float *e, float *temperature, const rte_temp_params *temp,
+                           void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!e || !temperature) return fail(RTE_ERR_INVALID_ARG, "null input or output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    if (int rc = ensure_lut(plan, temp, s)) return rc;
+    RTE_LAUNCH(plan, RTE_KERNEL_TEMP_MAP, s,
+               rte::launch_temp_invert(plan, e, temperature, temp->lut_size, temp->channel, temp->t_min,
+                                       temp->t_max, s));
+    return ok();
+}
+
+int rte_temperature_lut(rte_plan *plan, const rte_temp_params *temp, float *lut_host, int32_t lut_size)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!temp || !lut_host || lut_size != temp->lut_size)
+        return fail(RTE_ERR_INVALID_ARG, "null arguments or lut_size mismatch");
+    if (int rc = ensure_lut(plan, temp, plan->last_stream)) return rc;
+    std::memcpy(lut_host, plan->lut_host.data(), sizeof(float) * 3 * (size_t)lut_size);
+    return ok();
+}
+
+int rte_plan_set_timing(rte_plan *plan, int32_t enable)
+{
+    if (int rc = check_plan(plan)) return rc;
+    drain_timing(plan);
+    plan->timing = enable != 0;
+    for (int k = 0; k < RTE_KERNEL_COUNT; ++k) {
+        plan->kernel_ms[k] = 0.0;
+        plan->kernel_launches[k] = 0;
+    }
+    if (plan->timing && plan->event_pool.empty()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return fail(RTE_ERR_HIP, "hipEventCreate failed");
+            plan->event_pool.push_back(e);
+        }
+    }
+    return ok();
+}
+
+int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (kernel < 0 || kernel >= RTE_KERNEL_COUNT) return fail(RTE_ERR_INVALID_ARG, "unknown kernel id %d", kernel);
+    drain_timing(plan);
+    if (total_ms) *total_ms = plan->kernel_ms[kernel];
+    if (launches) *launches = plan->kernel_launches[kernel];
+    return ok();
+}
+
+}  // extern "C"

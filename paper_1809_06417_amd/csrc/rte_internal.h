@@ -1,0 +1,140 @@
+// Internal declarations shared by the translation units of librte.
+// Not part of the public ABI (include/rte.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rte.h"
+
+namespace rte {
+
+// One wave64 marches one 8x8 pixel tile: a pixel tile is the unit of the
+// per-sample weight buffer ("g buffer"), laid out [tile][k][lane], so that the
+// 64 rays of a wave write one contiguous 256-byte row per march step.
+constexpr int kTile = 8;
+constexpr int kTileRays = kTile * kTile;
+
+// Back-projection / epilogue selectors shared by launch wrappers and kernels.
+enum ResidualMode : int {
+    kEpiImage = 0,  // write I_c
+    kEpiSart = 1,   // y_c = (F_c - I_c) / R, R = sum_k g_k (0 where R = 0)
+    kEpiMlem = 2,   // y_c = F_c / I_c (1 where I_c <= 0)
+    kEpiPaper = 3,  // y_c = F_c - I_c
+};
+
+enum GatherMode : int {
+    kGatherAdjoint = 0,       // acc_c += g * y_c * w
+    kGatherAdjointCols = 1,   // acc_c += g * y_c * w ; acc_C += g * w
+    kGatherCols = 2,          // acc_0 += g * w
+    kGatherPaper = 3,         // acc_c += alpha_l y_c (1-tau)^k exp(-alpha_d D)
+};
+
+enum UpdateMode : int {
+    kUpdDelta = 0,   // out[c][j] = sum
+    kUpdCols = 1,    // cols[j] = sum
+    kUpdSart = 2,    // e += lambda sum / cols (cols > 0)
+    kUpdMlem = 3,    // e *= 1 + lambda (sum / cols - 1) (cols > 0)
+    kUpdPaper = 4,   // e += sum
+    kUpdTemp = 5,    // EM on the fitted channel, clamp to LUT, invert to T
+};
+
+// Per-view projection from voxel coordinates to homogeneous pixel
+// coordinates: (hu, hv, hw) = P[0..3] . (X,1), P[4..7] . (X,1), P[8..11] . (X,1).
+struct ViewProj {
+    float P[12];
+};
+
+struct GridDev {
+    int nx, ny, nz;
+    float ds;      // march step, world units
+    float inv_ds;
+};
+
+struct TimingRecord {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace rte
+
+struct rte_plan {
+    // configuration
+    rte_grid grid{};
+    rte_render_params params{};
+    std::vector<rte_camera> cams;
+    int V = 0, W = 0, H = 0;
+    int tiles_x = 0, tiles_y = 0, tiles_per_view = 0, n_tiles = 0;
+    int64_t n_rays = 0, n_nodes = 0, n_cells = 0;
+    double h[3] = {0, 0, 0};
+    double ds = 0.0;
+    uint64_t samples = 0, hit_rays = 0, g_floats = 0;
+    hipStream_t last_stream = nullptr;
+
+    // device workspaces (all owned by the plan)
+    rte_camera *d_cams = nullptr;
+    rte::ViewProj *d_proj = nullptr;
+    float4 *d_rayA = nullptr;       // entry point (voxel coords) xyz, chord length w
+    float4 *d_rayB = nullptr;       // direction (voxel units per world unit) xyz, K (int bits) w
+    float *d_tnear = nullptr;       // entry distance (export only)
+    int32_t *d_tile_kmax = nullptr;
+    uint64_t *d_tile_off = nullptr;
+    float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]
+    float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)
+    float4 *d_scat = nullptr;       // packed in-scatter grid (rgb, 0)
+    float4 *d_dirs = nullptr;       // in-scatter directions, voxel units per world unit
+    float *d_y = nullptr;           // per-pixel residual values [V][C][H][W]
+    float *d_part = nullptr;        // per-cell corner partials [8][acc][cells]
+    float *d_cols = nullptr;        // column sums A^T 1 [N]
+    float *d_lut = nullptr;         // [3][lut_cap]
+    int lut_cap = 0;
+    int part_acc = 0;               // accumulators per corner the partial buffer holds
+    size_t device_bytes = 0;
+
+    // LUT cache key
+    bool lut_valid = false;
+    rte_temp_params lut_params{};
+    std::vector<float> lut_host;
+
+    // timing
+    bool timing = false;
+    std::vector<rte::TimingRecord> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[RTE_KERNEL_COUNT] = {0};
+    int64_t kernel_launches[RTE_KERNEL_COUNT] = {0};
+};
+
+namespace rte {
+
+// ---- launch wrappers (rte_kernels.hip) ----
+hipError_t launch_ray_table(const rte_plan *p, hipStream_t s);
+hipError_t launch_tile_kmax(const rte_plan *p, hipStream_t s);
+hipError_t launch_ray_export(const rte_plan *p, float *t_near, float *t_far, int32_t *nseg,
+                             hipStream_t s);
+hipError_t launch_pack(const rte_plan *p, const float *emission, const float *extinction,
+                       int channels, hipStream_t s);
+hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s);
+hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
+hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
+                         bool write_g, int epilogue, const float *frames, int frame_channels,
+                         int frame_channel0, float *out, hipStream_t s);
+hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
+hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,
+                         float alpha_l, float alpha_d, float tau, hipStream_t s);
+hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
+                         int clamp_nonneg, float *out, float *temperature, int lut_size,
+                         int fit_channel, hipStream_t s);
+hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, float *sig_planar,
+                           bool packed, int lut_size, int fit_channel, float sigma_max,
+                           float soot_t0, float soot_span, float t_min, float t_max,
+                           hipStream_t s);
+hipError_t launch_temp_invert(const rte_plan *p, const float *e, float *T, int lut_size,
+                              int fit_channel, float t_min, float t_max, hipStream_t s);
+
+// ---- host LUT builder (rte_lut.cpp) ----
+void build_temperature_lut(const rte_temp_params &tp, std::vector<float> &lut);
+
+}  // namespace rte

@@ -1,0 +1,1108 @@
+// HIP kernels of librte for gfx950 (MI355X, CDNA4, wave64).
+//
+// K4 ray table   : once per plan, FP64 ray/box geometry per pixel ray.
+// K1 render      : one work-item per pixel ray, one wave per 8x8 pixel tile,
+//                  front-to-back march (Eq. 5-8) with fused residual epilogue
+//                  and optional per-sample weight output.
+// K2 in-scatter  : 32 lanes per in-scatter node, one direction per lane,
+//                  fixed-order butterfly sum (Eq. 5 third term, Eq. 9, g = 0).
+// K3 gather      : atomics-free back-projection (Alg. 2 adjustment): each
+//                  work-item owns one voxel (cell) and gathers, per view, the
+//                  samples of the rays through that cell into per-corner
+//                  partial sums; an assembly pass sums the eight cells around
+//                  every key point in a fixed order and applies the update.
+// K5 temperature : LUT map T -> (eps, sigma) and its inverse (Eq. 13).
+//
+// No float atomics anywhere: every sum has a fixed order, so results are
+// bitwise reproducible run to run.
+#include <cmath>
+
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ helpers
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give XCD x a contiguous range of logical blocks so that neighbouring
+// tiles / bricks share an L2. nb8 is the launched grid (a multiple of 8).
+__device__ __forceinline__ int xcd_remap(int b, int nb8)
+{
+    const int per = nb8 >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+static inline int grid8(int64_t blocks) { return (int)(((blocks + 7) / 8) * 8); }
+
+// Segment k of a chord of length L marched with step ds: midpoint offset s
+// from the entry and length len; the last segment is clipped at the exit.
+__device__ __forceinline__ void segment_of(int k, int K, float L, float ds, float &s, float &len)
+{
+    if (k < K - 1) {
+        s = ((float)k + 0.5f) * ds;
+        len = ds;
+    } else {
+        const float a = (float)k * ds;
+        len = fminf(fmaxf(L - a, 0.0f), ds);
+        s = fmaf(0.5f, len, a);
+    }
+}
+
+// Clamp a grid coordinate to [0, n-1] and split it into a cell index
+// (<= n-2) and the fraction inside the cell.
+__device__ __forceinline__ void cell_of(float x, int n, int &i, float &f)
+{
+    x = fminf(fmaxf(x, 0.0f), (float)(n - 1));
+    i = min((int)x, n - 2);
+    f = x - (float)i;
+}
+
+// Trilinear weights of the 8 cell corners, corner index = dx + 2 dy + 4 dz.
+__device__ __forceinline__ void tri_weights(float fx, float fy, float fz, float w[8])
+{
+    const float ax0 = 1.0f - fx, ay0 = 1.0f - fy, az0 = 1.0f - fz;
+    const float b00 = ay0 * az0, b10 = fy * az0, b01 = ay0 * fz, b11 = fy * fz;
+    w[0] = ax0 * b00;
+    w[1] = fx * b00;
+    w[2] = ax0 * b10;
+    w[3] = fx * b10;
+    w[4] = ax0 * b01;
+    w[5] = fx * b01;
+    w[6] = ax0 * b11;
+    w[7] = fx * b11;
+}
+
+// phi(x) = (1 - e^-x) / x (segment-averaged transmittance) and e = e^-x.
+// Taylor series below x = 0.25 (truncation < 2e-9), direct form above.
+__device__ __forceinline__ float phi_exp(float x, float &e)
+{
+    e = __expf(-x);
+    const float ser =
+        fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f), 1.0f / 120.0f),
+                                          -1.0f / 24.0f),
+                             1.0f / 6.0f),
+                  -0.5f),
+             1.0f);
+    const float dir = __fdividef(1.0f - e, x);
+    return x < 0.25f ? ser : dir;
+}
+
+template <int C> struct Packed;
+template <> struct Packed<1> { using T = float2; };
+template <> struct Packed<3> { using T = float4; };
+
+// Trilinear sample of the packed volume: emission channels and extinction.
+template <int C>
+__device__ __forceinline__ void sample_volume(const typename Packed<C>::T *__restrict__ vol, int nx,
+                                              int nxy, int ix, int iy, int iz, const float w[8],
+                                              float em[C], float &sig)
+{
+    const int base = (iz * nxy + iy * nx) + ix;
+    const int off[8] = {0, 1, nx, nx + 1, nxy, nxy + 1, nxy + nx, nxy + nx + 1};
+    sig = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) em[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const auto v = vol[base + off[c]];
+        if constexpr (C == 3) {
+            em[0] = fmaf(w[c], v.x, em[0]);
+            em[1] = fmaf(w[c], v.y, em[1]);
+            em[2] = fmaf(w[c], v.z, em[2]);
+            sig = fmaf(w[c], v.w, sig);
+        } else {
+            em[0] = fmaf(w[c], v.x, em[0]);
+            sig = fmaf(w[c], v.y, sig);
+        }
+    }
+}
+
+// ------------------------------------------------------------- K4 ray table
+
+struct RayArgs {
+    const rte_camera *cams;
+    float4 *rayA, *rayB;
+    float *tnear;
+    int W, H, V;
+    double lo[3], hi[3], h[3];
+    double ds;
+};
+
+// FP64 geometry: pinhole direction R^T K^-1 (u+1/2, v+1/2, 1), slab entry and
+// exit, K = ceil(chord / step). Contraction is off so the integer segment
+// count is decided by correctly rounded IEEE operations.
+__global__ __launch_bounds__(kBlock) void ray_table_kernel(RayArgs a)
+{
+#pragma clang fp contract(off)
+    const int64_t HW = (int64_t)a.W * a.H;
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= HW * a.V) return;
+    const int v = (int)(r / HW);
+    const int64_t pix = r - (int64_t)v * HW;
+    const int py = (int)(pix / a.W), px = (int)(pix - (int64_t)py * a.W);
+    const rte_camera &c = a.cams[v];
+    const double dc0 = ((double)px + 0.5 - c.cx) / c.fx;
+    const double dc1 = ((double)py + 0.5 - c.cy) / c.fy;
+    const double dc2 = 1.0;
+    double d[3], o[3], n2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        d[i] = c.R[0 * 3 + i] * dc0 + c.R[1 * 3 + i] * dc1 + c.R[2 * 3 + i] * dc2;
+        o[i] = -(c.R[0 * 3 + i] * c.t[0] + c.R[1 * 3 + i] * c.t[1] + c.R[2 * 3 + i] * c.t[2]);
+        n2 += d[i] * d[i];
+    }
+    const double inv = 1.0 / sqrt(n2);
+    for (int i = 0; i < 3; ++i) d[i] *= inv;
+    double t0 = -INFINITY, t1 = INFINITY;
+    bool hit = true;
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] != 0.0) {
+            double ta = (a.lo[i] - o[i]) / d[i], tb = (a.hi[i] - o[i]) / d[i];
+            if (ta > tb) {
+                const double s = ta;
+                ta = tb;
+                tb = s;
+            }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        } else if (o[i] < a.lo[i] || o[i] > a.hi[i]) {
+            hit = false;
+        }
+    }
+    if (t0 < 0.0) t0 = 0.0;
+    hit = hit && (t1 > t0);
+    int K = 0;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (hit) {
+        K = (int)ceil((t1 - t0) / a.ds);
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = (o[i] + t0 * d[i] - a.lo[i]) / a.h[i];
+        A = make_float4((float)p[0], (float)p[1], (float)p[2], (float)(t1 - t0));
+        B = make_float4((float)(d[0] / a.h[0]), (float)(d[1] / a.h[1]), (float)(d[2] / a.h[2]), 0.f);
+    }
+    B.w = __int_as_float(K);
+    a.rayA[r] = A;
+    a.rayB[r] = B;
+    a.tnear[r] = hit ? (float)t0 : 0.0f;
+}
+
+struct TileArgs {
+    const float4 *rayB;
+    int32_t *kmax;
+    int W, H, tiles_x, tiles_per_view, n_tiles;
+};
+
+// Maximum segment count of every 8x8 tile (sizes the per-sample weight rows).
+__global__ __launch_bounds__(kTileRays) void tile_kmax_kernel(TileArgs a)
+{
+    const int tile = blockIdx.x;
+    if (tile >= a.n_tiles) return;
+    const int lane = threadIdx.x;
+    const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    int K = 0;
+    if (px < a.W && py < a.H)
+        K = __float_as_int(a.rayB[((int64_t)v * a.H + py) * a.W + px].w);
+    for (int off = 32; off > 0; off >>= 1) K = max(K, __shfl_xor(K, off, 64));
+    if (lane == 0) a.kmax[tile] = K;
+}
+
+struct ExportArgs {
+    const float4 *rayA, *rayB;
+    const float *tnear;
+    float *t_near, *t_far;
+    int32_t *nseg;
+    int64_t n;
+};
+
+__global__ __launch_bounds__(kBlock) void ray_export_kernel(ExportArgs a)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= a.n) return;
+    const int K = __float_as_int(a.rayB[r].w);
+    const float tn = a.tnear[r];
+    if (a.t_near) a.t_near[r] = tn;
+    if (a.t_far) a.t_far[r] = K > 0 ? tn + a.rayA[r].w : 0.0f;
+    if (a.nseg) a.nseg[r] = K;
+}
+
+// ----------------------------------------------------------------- packing
+
+struct PackArgs {
+    const float *em, *sig;
+    float *vol;
+    int64_t n;
+};
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void pack_kernel(PackArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    const float s = a.sig ? a.sig[j] : 0.0f;
+    if constexpr (C == 3) {
+        float4 v = make_float4(0.f, 0.f, 0.f, s);
+        if (a.em) {
+            v.x = a.em[j];
+            v.y = a.em[a.n + j];
+            v.z = a.em[2 * a.n + j];
+        }
+        reinterpret_cast<float4 *>(a.vol)[j] = v;
+    } else {
+        reinterpret_cast<float2 *>(a.vol)[j] = make_float2(a.em ? a.em[j] : 0.0f, s);
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void unpack_kernel(PackArgs a, float *em)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    if constexpr (C == 3) {
+        const float4 v = reinterpret_cast<const float4 *>(a.vol)[j];
+        em[j] = v.x;
+        em[a.n + j] = v.y;
+        em[2 * a.n + j] = v.z;
+    } else {
+        em[j] = reinterpret_cast<const float2 *>(a.vol)[j].x;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void pack_scatter_kernel(const float *planar, float4 *out, int C,
+                                                             int64_t m3)
+{
+    const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (m >= m3) return;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    v.x = planar[m];
+    if (C == 3) {
+        v.y = planar[m3 + m];
+        v.z = planar[2 * m3 + m];
+    }
+    out[m] = v;
+}
+
+// ---------------------------------------------------------------- K1 render
+
+struct RenderArgs {
+    const float4 *rayA, *rayB;
+    const uint64_t *tile_off;
+    const float *vol;
+    const float4 *scat;
+    const float *frames;
+    float *out;
+    float *g;
+    int fC, fc0;  // frames hold fC channels; channel c of the render reads fc0 + c
+    int W, H, tiles_x, tiles_per_view, n_tiles, nb8;
+    int nx, ny, nz, M;
+    float ds, albedo, background;
+    float s_scale[3];  // fine grid coords -> in-scatter grid coords
+};
+
+// One work-item per pixel ray; a block holds four 8x8 tiles (one per wave).
+// EMIS: read the emission (false: weights only). SCAT: add in-scattering.
+// WRITE_G: store the per-sample weight g_k = T_k Delta_k phi_k.
+template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
+__global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = xcd_remap(blockIdx.x, a.nb8) * 4 + wave;
+    if (tile >= a.n_tiles) return;
+    const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    if (px >= a.W || py >= a.H) return;
+    const int HW = a.W * a.H;
+    const int pix = py * a.W + px;
+    const int r = v * HW + pix;
+    const float4 A = a.rayA[r], B = a.rayB[r];
+    const int K = __float_as_int(B.w);
+    const auto *vol = reinterpret_cast<const typename Packed<C>::T *>(a.vol);
+    const int nxy = a.nx * a.ny;
+    float I[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) I[c] = 0.0f;
+    float T = 1.0f, Rsum = 0.0f;
+    float *gp = nullptr;
+    if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
+    for (int k = 0; k < K; ++k) {
+        float s, len;
+        segment_of(k, K, A.w, a.ds, s, len);
+        const float x = fmaf(s, B.x, A.x), y = fmaf(s, B.y, A.y), z = fmaf(s, B.z, A.z);
+        int ix, iy, iz;
+        float fx, fy, fz;
+        cell_of(x, a.nx, ix, fx);
+        cell_of(y, a.ny, iy, fy);
+        cell_of(z, a.nz, iz, fz);
+        float w[8];
+        tri_weights(fx, fy, fz, w);
+        float em[C], sig;
+        sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, w, em, sig);
+        sig = fmaxf(sig, 0.0f);
+        if constexpr (SCAT) {
+            int jx, jy, jz;
+            float gx, gy, gz;
+            cell_of(x * a.s_scale[0], a.M, jx, gx);
+            cell_of(y * a.s_scale[1], a.M, jy, gy);
+            cell_of(z * a.s_scale[2], a.M, jz, gz);
+            float ws[8];
+            tri_weights(gx, gy, gz, ws);
+            const int M = a.M, MM = a.M * a.M;
+            const int base = jz * MM + jy * M + jx;
+            const int off[8] = {0, 1, M, M + 1, MM, MM + 1, MM + M, MM + M + 1};
+            float S[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float4 q = a.scat[base + off[c]];
+                S[0] = fmaf(ws[c], q.x, S[0]);
+                S[1] = fmaf(ws[c], q.y, S[1]);
+                S[2] = fmaf(ws[c], q.z, S[2]);
+            }
+            const float as = a.albedo * sig;
+#pragma unroll
+            for (int c = 0; c < C; ++c) em[c] = fmaf(as, S[c], em[c]);
+        }
+        float e;
+        const float ph = phi_exp(sig * len, e);
+        const float wg = T * len * ph;
+        if constexpr (EMIS) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) I[c] = fmaf(wg, em[c], I[c]);
+        }
+        Rsum += wg;
+        if constexpr (WRITE_G) gp[k * kTileRays] = wg;
+        T *= e;
+    }
+    if constexpr (EPI == kEpiImage) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
+    } else if constexpr (EPI == kEpiSart) {
+        const float inv = Rsum > 0.0f ? 1.0f / Rsum : 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = (v * C + c) * HW + pix;
+            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
+            a.out[i] = (F - fmaf(T, a.background, I[c])) * inv;
+        }
+    } else if constexpr (EPI == kEpiMlem) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = (v * C + c) * HW + pix;
+            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
+            const float It = fmaf(T, a.background, I[c]);
+            a.out[i] = It > 0.0f ? F / It : 1.0f;
+        }
+    } else if constexpr (EPI == kEpiPaper) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = (v * C + c) * HW + pix;
+            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
+            a.out[i] = F - fmaf(T, a.background, I[c]);
+        }
+    }
+}
+
+// ----------------------------------------------------------- K2 in-scatter
+
+struct ScatArgs {
+    const float *vol;
+    const float4 *dirs;  // unit directions in voxel units per world unit (xyz)
+    float4 *scat;        // packed output (rgb, 0)
+    float *planar;       // optional [C][M^3]
+    int nx, ny, nz, M, ndirs;
+    float p_scale[3];    // in-scatter node index -> fine grid coords
+    float ds;            // world step
+    float inv_ndirs;
+};
+
+// 32 lanes per node (lane l takes directions l, l+32, ...), 8 nodes per
+// block; the 32 partial sums are combined by a fixed xor butterfly and lane 0
+// of each group stores the node value.
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_kernel(ScatArgs a)
+{
+    const int grp = threadIdx.x >> 5, l = threadIdx.x & 31;
+    const int M = a.M;
+    const int m = blockIdx.x * 8 + grp;
+    if (m >= M * M * M) return;  // whole 32-lane group leaves together
+    const int mx = m % M, my = (m / M) % M, mz = m / (M * M);
+    const float px = (float)mx * a.p_scale[0], py = (float)my * a.p_scale[1],
+                pz = (float)mz * a.p_scale[2];
+    const float tx = (float)(a.nx - 1), ty = (float)(a.ny - 1), tz = (float)(a.nz - 1);
+    const auto *vol = reinterpret_cast<const typename Packed<C>::T *>(a.vol);
+    const int nxy = a.nx * a.ny;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    for (int d = l; d < a.ndirs; d += 32) {
+        const float4 u = a.dirs[d];
+        // exit distance from an interior point (world units)
+        float ell = INFINITY;
+        if (u.x > 0.f) ell = fminf(ell, (tx - px) / u.x);
+        if (u.x < 0.f) ell = fminf(ell, -px / u.x);
+        if (u.y > 0.f) ell = fminf(ell, (ty - py) / u.y);
+        if (u.y < 0.f) ell = fminf(ell, -py / u.y);
+        if (u.z > 0.f) ell = fminf(ell, (tz - pz) / u.z);
+        if (u.z < 0.f) ell = fminf(ell, -pz / u.z);
+        ell = fmaxf(ell, 0.0f);
+        const int K = ell > 0.0f ? (int)ceilf(ell / a.ds) : 0;
+        float T = 1.0f;
+        for (int k = 0; k < K; ++k) {
+            float s, len;
+            segment_of(k, K, ell, a.ds, s, len);
+            int ix, iy, iz;
+            float fx, fy, fz;
+            cell_of(fmaf(s, u.x, px), a.nx, ix, fx);
+            cell_of(fmaf(s, u.y, py), a.ny, iy, fy);
+            cell_of(fmaf(s, u.z, pz), a.nz, iz, fz);
+            float w[8];
+            tri_weights(fx, fy, fz, w);
+            float em[C], sig;
+            sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, w, em, sig);
+            sig = fmaxf(sig, 0.0f);
+            float e;
+            const float wg = T * len * phi_exp(sig * len, e);
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(wg, em[c], acc[c]);
+            T *= e;
+        }
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off, 32);
+    if (l == 0) {
+        float4 o = make_float4(acc[0] * a.inv_ndirs, 0.f, 0.f, 0.f);
+        if constexpr (C == 3) {
+            o.y = acc[1] * a.inv_ndirs;
+            o.z = acc[2] * a.inv_ndirs;
+        }
+        a.scat[m] = o;
+        if (a.planar) {
+            const int m3 = M * M * M;
+            a.planar[m] = o.x;
+            if constexpr (C == 3) {
+                a.planar[m3 + m] = o.y;
+                a.planar[2 * m3 + m] = o.z;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- K3 gather
+
+struct GatherArgs {
+    const float4 *rayA, *rayB;
+    const uint64_t *tile_off;
+    const float *g;
+    const float *y;        // [V][C][H][W]
+    const ViewProj *proj;
+    float *part;           // [8][acc][cells]
+    int V, W, H, tiles_x, tiles_per_view;
+    int nx, ny, nz;
+    int bx, by, bz, nb8;   // bricks of 8x8x4 cells
+    int ncells;
+    float ds, inv_ds;
+    float alpha_l, alpha_d, log2_keep;  // paper mode
+};
+
+constexpr float kBoxPad = 1e-3f;   // voxels: cell box padding for FP32 sample positions
+constexpr float kPixPad = 2e-3f;   // pixels: projection rounding allowance
+
+template <int C, int MODE>
+struct GatherAcc {
+    static constexpr int N = MODE == kGatherCols ? 1 : (MODE == kGatherAdjointCols ? C + 1 : C);
+};
+
+// Each work-item owns one cell (voxel) c and gathers every sample that the
+// render march placed in c: for each view it projects the (slightly padded)
+// cell box to a pixel rectangle, intersects each candidate pixel ray with the
+// box to bound the sample indices, and re-derives every candidate sample's
+// position exactly as the render did; only samples whose cell is c are kept.
+// The trilinear weights of the sample distribute its contribution to the
+// cell's 8 corners. Sums run in a fixed order: views, then pixels row-major,
+// then samples.
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
+{
+    constexpr int NA = GatherAcc<C, MODE>::N;
+    const int b = xcd_remap(blockIdx.x, a.nb8);
+    if (b >= a.bx * a.by * a.bz) return;
+    const int bxi = b % a.bx, byi = (b / a.bx) % a.by, bzi = b / (a.bx * a.by);
+    const int cx = bxi * 8 + (threadIdx.x & 7);
+    const int cy = byi * 8 + ((threadIdx.x >> 3) & 7);
+    const int cz = bzi * 4 + (threadIdx.x >> 6);
+    if (cx >= a.nx - 1 || cy >= a.ny - 1 || cz >= a.nz - 1) return;
+
+    float acc[8][NA];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[c][q] = 0.0f;
+
+    const float lo[3] = {(float)cx - kBoxPad, (float)cy - kBoxPad, (float)cz - kBoxPad};
+    const float hi[3] = {(float)cx + 1.0f + kBoxPad, (float)cy + 1.0f + kBoxPad,
+                         (float)cz + 1.0f + kBoxPad};
+    const int HW = a.W * a.H;
+
+    for (int v = 0; v < a.V; ++v) {
+        const float *P = a.proj[v].P;
+        // project the 8 corners of the padded box
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        bool behind = false;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float X = (c & 1) ? hi[0] : lo[0];
+            const float Y = (c & 2) ? hi[1] : lo[1];
+            const float Z = (c & 4) ? hi[2] : lo[2];
+            const float hu = fmaf(P[0], X, fmaf(P[1], Y, fmaf(P[2], Z, P[3])));
+            const float hv = fmaf(P[4], X, fmaf(P[5], Y, fmaf(P[6], Z, P[7])));
+            const float hw = fmaf(P[8], X, fmaf(P[9], Y, fmaf(P[10], Z, P[11])));
+            behind = behind || !(hw > 1e-6f);
+            const float iw = __builtin_amdgcn_rcpf(hw);
+            const float u = hu * iw, vv = hv * iw;
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+            vmin = fminf(vmin, vv);
+            vmax = fmaxf(vmax, vv);
+        }
+        int u0 = 0, u1 = a.W - 1, v0 = 0, v1 = a.H - 1;
+        if (!behind) {
+            u0 = max(u0, (int)ceilf(umin - 0.5f - kPixPad));
+            u1 = min(u1, (int)floorf(umax - 0.5f + kPixPad));
+            v0 = max(v0, (int)ceilf(vmin - 0.5f - kPixPad));
+            v1 = min(v1, (int)floorf(vmax - 0.5f + kPixPad));
+        }
+        for (int py = v0; py <= v1; ++py) {
+            for (int px = u0; px <= u1; ++px) {
+                const int pix = py * a.W + px;
+                const int r = v * HW + pix;
+                const float4 B = a.rayB[r];
+                const int K = __float_as_int(B.w);
+                if (K == 0) continue;
+                const float4 A = a.rayA[r];
+                // slab test against the padded cell box, in ray offset s
+                float s_in = 0.0f, s_out = A.w;
+                {
+                    const float pa[3] = {A.x, A.y, A.z};
+                    const float da[3] = {B.x, B.y, B.z};
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const float id = __builtin_amdgcn_rcpf(da[ax]);
+                        const float t0 = (lo[ax] - pa[ax]) * id, t1 = (hi[ax] - pa[ax]) * id;
+                        s_in = fmaxf(s_in, fminf(t0, t1));
+                        s_out = fminf(s_out, fmaxf(t0, t1));
+                    }
+                }
+                if (!(s_out >= s_in)) continue;
+                const int k_lo = max(0, (int)floorf(fmaf(s_in, a.inv_ds, -0.5f)));
+                const int k_hi = min(K - 1, (int)ceilf(fmaf(s_out, a.inv_ds, -0.5f)));
+                if (k_lo > k_hi) continue;
+                float yv[C];
+                if constexpr (MODE != kGatherCols) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) yv[c] = a.y[(v * C + c) * HW + pix];
+                }
+                const int tile = v * a.tiles_per_view + (py >> 3) * a.tiles_x + (px >> 3);
+                const float *gp = a.g + a.tile_off[tile] + ((py & 7) * 8 + (px & 7));
+                for (int k = k_lo; k <= k_hi; ++k) {
+                    float s, len;
+                    segment_of(k, K, A.w, a.ds, s, len);
+                    int ix, iy, iz;
+                    float fx, fy, fz;
+                    cell_of(fmaf(s, B.x, A.x), a.nx, ix, fx);
+                    cell_of(fmaf(s, B.y, A.y), a.ny, iy, fy);
+                    cell_of(fmaf(s, B.z, A.z), a.nz, iz, fz);
+                    if (ix != cx || iy != cy || iz != cz) continue;
+                    if constexpr (MODE == kGatherPaper) {
+                        const float keep = exp2f((float)k * a.log2_keep);
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            const float ddx = fx - (float)(c & 1);
+                            const float ddy = fy - (float)((c >> 1) & 1);
+                            const float ddz = fz - (float)((c >> 2) & 1);
+                            const float D = sqrtf(fmaf(ddx, ddx, fmaf(ddy, ddy, ddz * ddz)));
+                            const float amp = a.alpha_l * keep * __expf(-a.alpha_d * D);
+#pragma unroll
+                            for (int q = 0; q < C; ++q) acc[c][q] = fmaf(amp, yv[q], acc[c][q]);
+                        }
+                    } else {
+                        const float gk = gp[k * kTileRays];
+                        float w[8];
+                        tri_weights(fx, fy, fz, w);
+                        if constexpr (MODE == kGatherCols) {
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gk, w[c], acc[c][0]);
+                        } else {
+                            float gy[C];
+#pragma unroll
+                            for (int q = 0; q < C; ++q) gy[q] = gk * yv[q];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) {
+#pragma unroll
+                                for (int q = 0; q < C; ++q) acc[c][q] = fmaf(gy[q], w[c], acc[c][q]);
+                                if constexpr (MODE == kGatherAdjointCols)
+                                    acc[c][C] = fmaf(gk, w[c], acc[c][C]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const int cell = (cz * (a.ny - 1) + cy) * (a.nx - 1) + cx;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) a.part[(int64_t)(c * NA + q) * a.ncells + cell] = acc[c][q];
+}
+
+// -------------------------------------------------------- assembly + update
+
+struct UpdateArgs {
+    const float *part;
+    float *vol;          // packed volume (updates)
+    float *cols;         // column sums (read, or written in kUpdCols)
+    float *out;          // delta [C][N] (kUpdDelta)
+    float *temperature;  // kUpdTemp output
+    const float *lut;    // [3][lut_cap]
+    int lut_cap, lut_size, fit_channel;
+    float t_min, t_max;
+    int nx, ny, nz, ncells, acc;
+    int64_t n;
+    float lambda;
+    int clamp_nonneg;
+};
+
+// Inverse of an increasing LUT row by bisection and linear interpolation.
+__device__ __forceinline__ float lut_invert(const float *row, int L, float x, float t_min, float t_max)
+{
+    if (!(x > row[0])) return t_min;
+    if (x >= row[L - 1]) return t_max;
+    int lo = 0, hi = L - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (row[mid] <= x) lo = mid; else hi = mid;
+    }
+    const float f = (x - row[lo]) / (row[hi] - row[lo]);
+    const float dT = (t_max - t_min) / (float)(L - 1);
+    return fmaf((float)lo + f, dT, t_min);
+}
+
+// Sum the 8 cells around key point j (fixed order: corner index of j in the
+// cell = dx + 2 dy + 4 dz) and apply the update rule.
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    const int jx = (int)(j % a.nx), jy = (int)((j / a.nx) % a.ny), jz = (int)(j / ((int64_t)a.nx * a.ny));
+    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : C);
+    float sum[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sum[q] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int cx = jx - (e & 1), cy = jy - ((e >> 1) & 1), cz = jz - ((e >> 2) & 1);
+        if (cx < 0 || cy < 0 || cz < 0 || cx > a.nx - 2 || cy > a.ny - 2 || cz > a.nz - 2) continue;
+        const int cell = (cz * (a.ny - 1) + cy) * (a.nx - 1) + cx;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sum[q] += a.part[(int64_t)(e * a.acc + q) * a.ncells + cell];
+    }
+    if constexpr (MODE == kUpdDelta) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) a.out[q * a.n + j] = sum[q];
+    } else if constexpr (MODE == kUpdCols) {
+        a.cols[j] = sum[0];
+    } else if constexpr (MODE == kUpdTemp) {
+        float2 *vol = reinterpret_cast<float2 *>(a.vol);
+        float2 p = vol[j];
+        float e = p.x;
+        const float cs = sum[1];
+        if (cs > 0.0f) e = e * fmaf(a.lambda, sum[0] / cs - 1.0f, 1.0f);
+        const float *row = a.lut + a.fit_channel * a.lut_cap;
+        e = fminf(fmaxf(e, row[0]), row[a.lut_size - 1]);
+        a.temperature[j] = lut_invert(row, a.lut_size, e, a.t_min, a.t_max);
+    } else {
+        const float cs = (MODE == kUpdPaper) ? 1.0f : a.cols[j];
+        if (MODE != kUpdPaper && !(cs > 0.0f)) return;
+        float em[C];
+        if constexpr (C == 3) {
+            const float4 p = reinterpret_cast<float4 *>(a.vol)[j];
+            em[0] = p.x;
+            em[1] = p.y;
+            em[2] = p.z;
+        } else {
+            em[0] = reinterpret_cast<float2 *>(a.vol)[j].x;
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            float e = em[q];
+            if constexpr (MODE == kUpdSart) e = fmaf(a.lambda, sum[q] / cs, e);
+            if constexpr (MODE == kUpdMlem) e = e * fmaf(a.lambda, sum[q] / cs - 1.0f, 1.0f);
+            if constexpr (MODE == kUpdPaper) e = e + sum[q];
+            if (a.clamp_nonneg) e = fmaxf(e, 0.0f);
+            em[q] = e;
+        }
+        if constexpr (C == 3) {
+            float4 *p = reinterpret_cast<float4 *>(a.vol) + j;
+            p->x = em[0];
+            p->y = em[1];
+            p->z = em[2];
+        } else {
+            reinterpret_cast<float2 *>(a.vol)[j].x = em[0];
+        }
+    }
+}
+
+// ------------------------------------------------------- K5 temperature map
+
+struct TempArgs {
+    const float *T;
+    const float *lut;
+    float *em;     // planar [3][N] or NULL
+    float *sig;    // planar [N] or NULL
+    float *vol;    // packed float2 (eps_fit, sigma) or NULL
+    int lut_cap, lut_size, fit_channel;
+    float t_min, t_max, sigma_max, soot_t0, soot_span;
+    int64_t n;
+};
+
+__device__ __forceinline__ float lut_lookup(const float *row, int L, float T, float t_min, float t_max)
+{
+    float pos = (T - t_min) / (t_max - t_min) * (float)(L - 1);
+    pos = fminf(fmaxf(pos, 0.0f), (float)(L - 1));
+    const int i = min((int)pos, L - 2);
+    const float f = pos - (float)i;
+    return fmaf(f, row[i + 1] - row[i], row[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void temp_map_kernel(TempArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    const float T = a.T[j];
+    const float sg = a.sigma_max * fmaxf(0.0f, (T - a.soot_t0) / a.soot_span);
+    if (a.em)
+        for (int c = 0; c < 3; ++c) a.em[c * a.n + j] = lut_lookup(a.lut + c * a.lut_cap, a.lut_size, T, a.t_min, a.t_max);
+    if (a.sig) a.sig[j] = sg;
+    if (a.vol) {
+        const float e = lut_lookup(a.lut + a.fit_channel * a.lut_cap, a.lut_size, T, a.t_min, a.t_max);
+        reinterpret_cast<float2 *>(a.vol)[j] = make_float2(e, sg);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void temp_invert_kernel(const float *e, float *T, const float *row,
+                                                            int L, float t_min, float t_max, int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const float x = fminf(fmaxf(e[j], row[0]), row[L - 1]);
+    T[j] = lut_invert(row, L, x, t_min, t_max);
+}
+
+static inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ------------------------------------------------------------ host launches
+
+hipError_t launch_ray_table(const rte_plan *p, hipStream_t s)
+{
+    RayArgs a{};
+    a.cams = p->d_cams;
+    a.rayA = p->d_rayA;
+    a.rayB = p->d_rayB;
+    a.tnear = p->d_tnear;
+    a.W = p->W;
+    a.H = p->H;
+    a.V = p->V;
+    for (int i = 0; i < 3; ++i) {
+        a.lo[i] = p->grid.bbox_min[i];
+        a.hi[i] = p->grid.bbox_max[i];
+        a.h[i] = p->h[i];
+    }
+    a.ds = p->ds;
+    hipLaunchKernelGGL(ray_table_kernel, dim3(blocks_for(p->n_rays)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_kmax(const rte_plan *p, hipStream_t s)
+{
+    TileArgs a{p->d_rayB, p->d_tile_kmax, p->W, p->H, p->tiles_x, p->tiles_per_view, p->n_tiles};
+    hipLaunchKernelGGL(tile_kmax_kernel, dim3(p->n_tiles), dim3(kTileRays), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_export(const rte_plan *p, float *t_near, float *t_far, int32_t *nseg,
+                             hipStream_t s)
+{
+    ExportArgs a{p->d_rayA, p->d_rayB, p->d_tnear, t_near, t_far, nseg, p->n_rays};
+    hipLaunchKernelGGL(ray_export_kernel, dim3(blocks_for(p->n_rays)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const rte_plan *p, const float *emission, const float *extinction,
+                       int channels, hipStream_t s)
+{
+    PackArgs a{emission, extinction, p->d_vol, p->n_nodes};
+    if (channels == 3)
+        hipLaunchKernelGGL(pack_kernel<3>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(pack_kernel<1>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s)
+{
+    PackArgs a{nullptr, nullptr, p->d_vol, p->n_nodes};
+    if (channels == 3)
+        hipLaunchKernelGGL(unpack_kernel<3>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a, emission);
+    else
+        hipLaunchKernelGGL(unpack_kernel<1>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a, emission);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s)
+{
+    const int64_t m3 = (int64_t)p->params.scatter_res * p->params.scatter_res * p->params.scatter_res;
+    hipLaunchKernelGGL(pack_scatter_kernel, dim3(blocks_for(m3)), dim3(kBlock), 0, s, planar, p->d_scat,
+                       (int)p->params.channels, m3);
+    return hipGetLastError();
+}
+
+template <int C, bool EMIS, bool SCAT, bool WG, int EPI>
+static void render_launch(const RenderArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((render_kernel<C, EMIS, SCAT, WG, EPI>), dim3(a.nb8), dim3(kBlock), 0, s, a);
+}
+
+template <int C>
+static hipError_t render_dispatch(const RenderArgs &a, bool emis, bool scat, bool wg, int epi,
+                                  hipStream_t s)
+{
+    if (!emis) {
+        // weights only (transmittance and per-sample weights); no epilogue
+        render_launch<C, false, false, true, -1>(a, s);
+        return hipGetLastError();
+    }
+#define RTE_EPI(E)                                                                        \
+    if (epi == E) {                                                                       \
+        if (scat && wg) render_launch<C, true, true, true, E>(a, s);                      \
+        else if (scat) render_launch<C, true, true, false, E>(a, s);                      \
+        else if (wg) render_launch<C, true, false, true, E>(a, s);                        \
+        else render_launch<C, true, false, false, E>(a, s);                               \
+        return hipGetLastError();                                                         \
+    }
+    RTE_EPI(kEpiImage)
+    RTE_EPI(kEpiSart)
+    RTE_EPI(kEpiMlem)
+    RTE_EPI(kEpiPaper)
+#undef RTE_EPI
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
+                         bool write_g, int epilogue, const float *frames, int frame_channels,
+                         int frame_channel0, float *out, hipStream_t s)
+{
+    RenderArgs a{};
+    a.fC = frame_channels;
+    a.fc0 = frame_channel0;
+    a.rayA = p->d_rayA;
+    a.rayB = p->d_rayB;
+    a.tile_off = p->d_tile_off;
+    a.vol = p->d_vol;
+    a.scat = p->d_scat;
+    a.frames = frames;
+    a.out = out;
+    a.g = p->d_g;
+    a.W = p->W;
+    a.H = p->H;
+    a.tiles_x = p->tiles_x;
+    a.tiles_per_view = p->tiles_per_view;
+    a.n_tiles = p->n_tiles;
+    a.nb8 = grid8((p->n_tiles + 3) / 4);
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.M = p->params.scatter_res;
+    a.ds = (float)p->ds;
+    a.albedo = p->params.albedo;
+    a.background = p->params.background;
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    for (int i = 0; i < 3; ++i)
+        a.s_scale[i] = a.M >= 2 ? (float)((double)(a.M - 1) / (double)(n[i] - 1)) : 0.0f;
+    if (channels == 3) return render_dispatch<3>(a, use_emission, use_scatter, write_g, epilogue, s);
+    return render_dispatch<1>(a, use_emission, use_scatter, write_g, epilogue, s);
+}
+
+hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
+{
+    ScatArgs a{};
+    a.vol = p->d_vol;
+    a.dirs = p->d_dirs;
+    a.scat = p->d_scat;
+    a.planar = planar_out;
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.M = p->params.scatter_res;
+    a.ndirs = p->params.scatter_dirs;
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    double hs_min = 1e300;
+    for (int i = 0; i < 3; ++i) {
+        a.p_scale[i] = (float)((double)(n[i] - 1) / (double)(a.M - 1));
+        const double hs = (p->grid.bbox_max[i] - p->grid.bbox_min[i]) / (double)(a.M - 1);
+        hs_min = hs < hs_min ? hs : hs_min;
+    }
+    a.ds = (float)(p->params.scatter_step * hs_min);
+    a.inv_ndirs = 1.0f / (float)a.ndirs;
+    const int64_t m3 = (int64_t)a.M * a.M * a.M;
+    const int nb = (int)((m3 + 7) / 8);
+    if (p->params.channels == 3)
+        hipLaunchKernelGGL(inscatter_kernel<3>, dim3(nb), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(inscatter_kernel<1>, dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int C, int MODE>
+static void gather_launch(const GatherArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((gather_kernel<C, MODE>), dim3(a.nb8), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y, float alpha_l,
+                         float alpha_d, float tau, hipStream_t s)
+{
+    GatherArgs a{};
+    a.rayA = p->d_rayA;
+    a.rayB = p->d_rayB;
+    a.tile_off = p->d_tile_off;
+    a.g = p->d_g;
+    a.y = y;
+    a.proj = p->d_proj;
+    a.part = p->d_part;
+    a.V = p->V;
+    a.W = p->W;
+    a.H = p->H;
+    a.tiles_x = p->tiles_x;
+    a.tiles_per_view = p->tiles_per_view;
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.bx = (a.nx - 1 + 7) / 8;
+    a.by = (a.ny - 1 + 7) / 8;
+    a.bz = (a.nz - 1 + 3) / 4;
+    a.nb8 = grid8((int64_t)a.bx * a.by * a.bz);
+    a.ncells = (int)p->n_cells;
+    a.ds = (float)p->ds;
+    a.inv_ds = (float)(1.0 / p->ds);
+    a.alpha_l = alpha_l;
+    a.alpha_d = alpha_d;
+    a.log2_keep = (float)std::log2(1.0 - (double)tau);
+    if (channels == 3) {
+        switch (mode) {
+        case kGatherAdjoint: gather_launch<3, kGatherAdjoint>(a, s); break;
+        case kGatherAdjointCols: gather_launch<3, kGatherAdjointCols>(a, s); break;
+        case kGatherCols: gather_launch<3, kGatherCols>(a, s); break;
+        case kGatherPaper: gather_launch<3, kGatherPaper>(a, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (mode) {
+        case kGatherAdjoint: gather_launch<1, kGatherAdjoint>(a, s); break;
+        case kGatherAdjointCols: gather_launch<1, kGatherAdjointCols>(a, s); break;
+        case kGatherCols: gather_launch<1, kGatherCols>(a, s); break;
+        case kGatherPaper: gather_launch<1, kGatherPaper>(a, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int C, int MODE>
+static void update_launch(const UpdateArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((update_kernel<C, MODE>), dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
+                         int clamp_nonneg, float *out, float *temperature, int lut_size,
+                         int fit_channel, hipStream_t s)
+{
+    UpdateArgs a{};
+    a.part = p->d_part;
+    a.vol = p->d_vol;
+    a.cols = p->d_cols;
+    a.out = out;
+    a.temperature = temperature;
+    a.lut = p->d_lut;
+    a.lut_cap = p->lut_cap;
+    a.lut_size = lut_size;
+    a.fit_channel = fit_channel;
+    a.t_min = p->lut_params.t_min;
+    a.t_max = p->lut_params.t_max;
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.ncells = (int)p->n_cells;
+    a.acc = acc;
+    a.n = p->n_nodes;
+    a.lambda = lambda;
+    a.clamp_nonneg = clamp_nonneg;
+#define RTE_UPD(M)                                            \
+    case M:                                                   \
+        if (channels == 3) update_launch<3, M>(a, s);         \
+        else update_launch<1, M>(a, s);                       \
+        break;
+    switch (mode) {
+        RTE_UPD(kUpdDelta)
+        RTE_UPD(kUpdCols)
+        RTE_UPD(kUpdSart)
+        RTE_UPD(kUpdMlem)
+        RTE_UPD(kUpdPaper)
+    case kUpdTemp: update_launch<1, kUpdTemp>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef RTE_UPD
+    return hipGetLastError();
+}
+
+hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, float *sig_planar,
+                           bool packed, int lut_size, int fit_channel, float sigma_max,
+                           float soot_t0, float soot_span, float t_min, float t_max, hipStream_t s)
+{
+    TempArgs a{};
+    a.T = T;
+    a.lut = p->d_lut;
+    a.em = em_planar;
+    a.sig = sig_planar;
+    a.vol = packed ? p->d_vol : nullptr;
+    a.lut_cap = p->lut_cap;
+    a.lut_size = lut_size;
+    a.fit_channel = fit_channel;
+    a.t_min = t_min;
+    a.t_max = t_max;
+    a.sigma_max = sigma_max;
+    a.soot_t0 = soot_t0;
+    a.soot_span = soot_span;
+    a.n = p->n_nodes;
+    hipLaunchKernelGGL(temp_map_kernel, dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_temp_invert(const rte_plan *p, const float *e, float *T, int lut_size,
+                              int fit_channel, float t_min, float t_max, hipStream_t s)
+{
+    hipLaunchKernelGGL(temp_invert_kernel, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, e, T,
+                       p->d_lut + (size_t)fit_channel * p->lut_cap, lut_size, t_min, t_max,
+                       p->n_nodes);
+    return hipGetLastError();
+}
+
+}  // namespace rte

@@ -137,17 +137,31 @@ def grid_nodes(grid: Grid):
     return X, Y, Z
 
 
+def blob_fields(grid: Grid, centres, covs, peaks) -> np.ndarray:
+    """Several fields sharing the same Gaussian blobs: field f is
+    sum_b peaks[b][f] * exp(-0.5 (x - c_b)^T cov_b^{-1} (x - c_b)) at every
+    key point. peaks has shape [n_blobs, n_fields]; returns [n_fields, nz, ny, nx]."""
+    xs = np.linspace(grid.lo[0], grid.hi[0], grid.nx)
+    ys = np.linspace(grid.lo[1], grid.hi[1], grid.ny)
+    zs = np.linspace(grid.lo[2], grid.hi[2], grid.nz)
+    peaks = np.asarray(peaks, float).reshape(len(centres), -1)
+    out = np.zeros((peaks.shape[1],) + grid.shape_zyx)
+    for c, cov, pk in zip(centres, covs, peaks):
+        A = np.linalg.inv(np.asarray(cov, float))
+        dx = (xs - c[0])[None, None, :]
+        dy = (ys - c[1])[None, :, None]
+        dz = (zs - c[2])[:, None, None]
+        q = (A[0, 0] * dx * dx + A[1, 1] * dy * dy + A[2, 2] * dz * dz
+             + 2.0 * A[0, 1] * dx * dy + 2.0 * A[0, 2] * dx * dz + 2.0 * A[1, 2] * dy * dz)
+        gb = np.exp(-0.5 * q)
+        for f in range(peaks.shape[1]):
+            out[f] += pk[f] * gb
+    return out
+
+
 def blob_field(grid: Grid, centres, covs, peaks) -> np.ndarray:
     """sum_b peak_b * exp(-0.5 (x - c_b)^T cov_b^{-1} (x - c_b)) at every key point."""
-    X, Y, Z = grid_nodes(grid)
-    P = np.stack([X, Y, Z], axis=-1)
-    out = np.zeros(grid.shape_zyx)
-    for c, cov, pk in zip(centres, covs, peaks):
-        d = P - np.asarray(c, float)
-        inv = np.linalg.inv(np.asarray(cov, float))
-        q = np.einsum("...i,ij,...j->...", d, inv, d)
-        out += pk * np.exp(-0.5 * q)
-    return out
+    return blob_fields(grid, centres, covs, np.asarray(peaks, float)[:, None])[0]
 
 
 def tiny_volume(seed: int = 0, n: int = 32, n_blobs: int = 3):
@@ -194,9 +208,8 @@ def colour_volume(seed: int = 0, n: int = 128, n_blobs: int = 20):
     rgb = np.array([[1.0, rng.uniform(0.4, 0.8), rng.uniform(0.1, 0.3)] for _ in range(n_blobs)])
     rgb *= rng.uniform(0.5, 1.0, size=(n_blobs, 1))
     sig_pk = rng.uniform(0.5, 4.0, size=n_blobs)
-    em = np.stack([blob_field(g, centres, covs, rgb[:, c]) for c in range(3)])
-    sig = blob_field(g, centres, covs, sig_pk)
-    return g, em, sig
+    fields = blob_fields(g, centres, covs, np.concatenate([rgb, sig_pk[:, None]], axis=1))
+    return g, fields[:3].copy(), fields[3].copy()
 
 
 def temperature_volume(seed: int = 0, n: int = 128, n_blobs: int = 20, t_bg: float = 800.0,

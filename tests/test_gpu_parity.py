@@ -1,0 +1,400 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded FP32 inputs. Expected values come only from the oracle (or from
+closed forms / properties that hold at any size)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import (BACKPROJ_REL, RENDER_REL, VOLUME_RMS, as64, dev, f32, host, rel_max, rel_rms,
+                      render_rel, say)
+
+pytestmark = pytest.mark.gpu
+
+STEP = 0.5
+
+
+def rte():
+    from paper_1809_06417_amd import rte as _rte
+    return _rte
+
+
+# ---------------------------------------------------------------- cases
+def blob_volume(grid, C, seed, n_blobs=4):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array(grid.lo), np.array(grid.hi)
+    centres = [lo + (hi - lo) * rng.uniform(0.25, 0.75, 3) for _ in range(n_blobs)]
+    ext = (hi - lo).min()
+    covs = [np.diag((ext * rng.uniform(0.08, 0.2, 3)) ** 2) for _ in range(n_blobs)]
+    peaks = rng.uniform(0.4, 1.0, size=(n_blobs, C + 1))
+    peaks[:, C] *= rng.uniform(1.0, 4.0) / max(ext, 1e-9)
+    f = synth.blob_fields(grid, centres, covs, peaks)
+    return f32(f[:C]), f32(f[C])
+
+
+def make_case(name):
+    if name == "tiny":
+        g, em, sig = synth.tiny_volume(seed=0)
+        rig = synth.ring_rig(4, 64, 64)
+        return dict(g=g, rig=rig, em=f32(em), sig=f32(sig), C=1, albedo=0.0, bg=0.0)
+    if name == "ragged":
+        g = synth.Grid(13, 11, 9, lo=(-0.2, 0.1, 0.0), hi=(1.1, 0.9, 0.7))
+        rig = synth.ring_rig(3, 37, 29, radius=2.4, fov_y_deg=45, centre=(0.45, 0.5, 0.35),
+                             elevation_jitter_deg=20, seed=5)
+        em, sig = blob_volume(g, 1, 11)
+        return dict(g=g, rig=rig, em=em, sig=sig, C=1, albedo=0.0, bg=0.0)
+    if name == "colour_small":
+        g = synth.Grid(24, 24, 24)
+        rig = synth.ring_rig(4, 40, 36, elevation_jitter_deg=12, seed=2)
+        em, sig = blob_volume(g, 3, 7, n_blobs=5)
+        return dict(g=g, rig=rig, em=em, sig=sig, C=3, albedo=0.3, bg=0.05, M=8, dirs=16)
+    raise KeyError(name)
+
+
+_CACHE = {}
+
+
+def case(name):
+    if name not in _CACHE:
+        _CACHE[name] = make_case(name)
+    return _CACHE[name]
+
+
+def plan_for(c, **kw):
+    args = dict(channels=c["C"], step_vox=STEP, albedo=c["albedo"], background=c["bg"],
+                scatter_res=c.get("M", 0), scatter_dirs=c.get("dirs", 32))
+    args.update(kw)
+    return rte().Plan(c["g"], c["rig"], **args)
+
+
+def oracle_S(c):
+    if not c.get("M"):
+        return None
+    if "S" not in c:
+        c["S"] = f32(oracle.inscatter(c["g"], as64(c["em"]), as64(c["sig"]), s_res=c["M"],
+                                      n_dirs=c["dirs"]))
+    return c["S"]
+
+
+def oracle_frames(c):
+    if "F" not in c:
+        S = oracle_S(c)
+        c["F"] = f32(oracle.render(c["g"], c["rig"], as64(c["em"]), as64(c["sig"]), step_vox=STEP,
+                                   albedo=c["albedo"], background=c["bg"],
+                                   inscatter=None if S is None else as64(S)))
+    return c["F"]
+
+
+CASES = ["tiny", "ragged", "colour_small"]
+
+
+# ------------------------------------------------------------ a1 ray table
+@pytest.mark.parametrize("name", CASES)
+def test_ray_table_matches_oracle(name):
+    c = case(name)
+    tn_o, tf_o, K_o = oracle.ray_table(c["g"], c["rig"], STEP)
+    say("ray_table", name)
+    with plan_for(c) as p:
+        tn, tf, K = p.ray_table()
+        K = K.cpu().numpy()
+        tn, tf = host(tn), host(tf)
+        assert p.samples == int(K_o.sum()) and p.hit_rays == int((K_o > 0).sum())
+    np.testing.assert_array_equal(K, K_o)  # integer segment counts: bit-exact
+    hit = K_o > 0
+    np.testing.assert_allclose(tn[hit], tn_o[hit], rtol=2e-7, atol=1e-6)
+    np.testing.assert_allclose(tf[hit], tf_o[hit], rtol=2e-7, atol=1e-6)
+
+
+# --------------------------------------------------------------- a2 render
+@pytest.mark.parametrize("name", CASES)
+def test_render_matches_oracle(name):
+    c = case(name)
+    S = oracle_S(c)
+    ref = oracle.render(c["g"], c["rig"], as64(c["em"]), as64(c["sig"]), step_vox=STEP,
+                        albedo=c["albedo"], background=c["bg"],
+                        inscatter=None if S is None else as64(S))
+    say("render", name)
+    with plan_for(c) as p:
+        img = host(p.render(dev(c["em"]), dev(c["sig"]), None if S is None else dev(S)))
+    assert img.shape == ref.shape
+    assert render_rel(img, ref) <= RENDER_REL
+
+
+def test_render_beer_lambert_closed_form():
+    """Constant medium: I = (eps/sigma)(1 - e^{-sigma L}) per pixel, L the chord."""
+    from test_oracle_pins import chords
+    g = synth.Grid(17, 15, 19)
+    rig = synth.ring_rig(3, 33, 27, radius=2.2, elevation_jitter_deg=20, seed=8)
+    eps, sig = 0.7, 2.3
+    say("beer_lambert")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        img = host(p.render(dev(np.full((1,) + g.shape_zyx, eps)), dev(np.full(g.shape_zyx, sig))))
+    for v in range(3):
+        _, _, tn, tf, hit = chords(rig, v)
+        L = tf - tn
+        ref = np.where(hit, eps / sig * -np.expm1(-sig * L), 0.0)
+        assert np.abs(img[v, 0] - ref).max() <= 1e-5 * ref.max()
+
+
+# ------------------------------------------------------------ a3 in-scatter
+@pytest.mark.parametrize("C", [3, 1])
+def test_inscatter_matches_oracle(C):
+    c = case("colour_small")
+    em = c["em"][:C]
+    ref = oracle.inscatter(c["g"], as64(em), as64(c["sig"]), s_res=c["M"], n_dirs=c["dirs"])
+    say("inscatter", C)
+    with rte().Plan(c["g"], c["rig"], channels=C, step_vox=STEP, albedo=0.3, scatter_res=c["M"],
+                    scatter_dirs=c["dirs"]) as p:
+        S = host(p.inscatter(dev(em), dev(c["sig"])))
+    assert rel_max(S, ref) <= RENDER_REL
+
+
+# ---------------------------------------------------- a5 back-projection
+@pytest.mark.parametrize("name", CASES)
+def test_backproject_adjoint_matches_oracle(name):
+    c = case(name)
+    V, H, W = c["rig"].n_views, c["rig"].height, c["rig"].width
+    y = f32(np.random.default_rng(3).normal(size=(V, c["C"], H, W)))
+    ref = oracle.backproject_adjoint(c["g"], c["rig"], as64(c["sig"]), as64(y), step_vox=STEP)
+    say("backproject_adjoint", name)
+    with plan_for(c) as p:
+        d = host(p.backproject(dev(c["sig"]), dev(y)))
+    assert rel_max(d, ref) <= BACKPROJ_REL
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_identity_on_gpu(name):
+    c = case(name)
+    V, H, W = c["rig"].n_views, c["rig"].height, c["rig"].width
+    rng = np.random.default_rng(4)
+    x = f32(rng.uniform(size=(c["C"],) + c["g"].shape_zyx))
+    y = f32(rng.normal(size=(V, c["C"], H, W)))
+    say("adjoint_identity", name)
+    with plan_for(c, albedo=0.0, background=0.0, scatter_res=0) as p:
+        Ax = host(p.render(dev(x), dev(c["sig"])))
+        ATy = host(p.backproject(dev(c["sig"]), dev(y)))
+    lhs, rhs = float((Ax * as64(y)).sum()), float((as64(x) * ATy).sum())
+    assert abs(lhs - rhs) <= 1e-5 * float(np.abs(Ax * as64(y)).sum())
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_backproject_paper_matches_oracle(name):
+    c = case(name)
+    V, H, W = c["rig"].n_views, c["rig"].height, c["rig"].width
+    dL = f32(np.random.default_rng(5).normal(size=(V, c["C"], H, W)))
+    ref = oracle.backproject_paper(c["g"], c["rig"], as64(dL), step_vox=STEP, alpha_l=1e-3,
+                                   alpha_d=1.0, tau=0.05)
+    say("backproject_paper", name)
+    with plan_for(c) as p:
+        d = host(p.backproject(None, dev(dL), mode="paper", alpha_l=1e-3, alpha_d=1.0, tau=0.05))
+    # a sample on a cell face may fall in either neighbouring cell under
+    # FP32 vs FP64 rounding: the set of touched key points changes there
+    assert rel_rms(d, ref) <= 1e-4
+    assert rel_max(d, ref) <= 2e-2
+
+
+def test_backproject_paper_worked_case_on_gpu():
+    from test_oracle_pins import axis_ray_rig
+    g = synth.Grid(5, 5, 5, lo=(0, 0, 0), hi=(4, 4, 4))
+    rig = axis_ray_rig()
+    say("paper_worked_case")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        d = host(p.backproject(None, dev(np.full((1, 1, 1, 1), 2.0)), mode="paper"))[0]
+    ref = np.zeros((5, 5, 5))
+    for k in range(8):
+        x = 3.75 - 0.5 * k
+        cx = int(math.floor(x))
+        for jx in (cx, cx + 1):
+            for jy in (2, 3):
+                for jz in (2, 3):
+                    D = math.sqrt((x - jx) ** 2 + (2 - jy) ** 2 + (2 - jz) ** 2)
+                    ref[jz, jy, jx] += 1e-3 * 2.0 * 0.95 ** k * math.exp(-D)
+    np.testing.assert_allclose(d, ref, rtol=2e-6, atol=1e-12)
+
+
+# ---------------------------------------------------- a4 + a6 reconstruction
+def test_tiny_workload_sart_matches_oracle():
+    """The tiny plain-method workload: 32^3, 4 views of 64^2, 5 SART
+    iterations from zero against renders of the ground truth."""
+    c = case("tiny")
+    F = oracle_frames(c)
+    ref = oracle.reconstruct(c["g"], c["rig"], as64(F), as64(c["sig"]), np.zeros(c["em"].shape), 5,
+                             step_vox=STEP)
+    say("reconstruct tiny sart")
+    with plan_for(c) as p:
+        x = host(p.reconstruct(dev(F), dev(c["sig"]), dev(np.zeros(c["em"].shape)), 5))
+    assert rel_rms(x, ref) <= VOLUME_RMS
+    # and the method itself makes progress on the ground truth
+    assert np.sqrt(((x - c["em"]) ** 2).mean()) < 0.5 * np.sqrt((c["em"] ** 2).mean())
+
+
+@pytest.mark.parametrize("update", ["mlem", "paper"])
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_reconstruct_update_rules_match_oracle(name, update):
+    c = case(name)
+    F = oracle_frames(c)
+    x0 = f32(np.full(c["em"].shape, 0.05))
+    ref = oracle.reconstruct(c["g"], c["rig"], as64(F), as64(c["sig"]), as64(x0), 5, step_vox=STEP,
+                             mode=update, clamp_nonneg=True)
+    say("reconstruct", name, update)
+    with plan_for(c) as p:
+        x = host(p.reconstruct(dev(F), dev(c["sig"]), dev(x0), 5, update=update))
+    assert rel_rms(x, ref) <= VOLUME_RMS
+
+
+def test_colour_with_inscatter_sart_matches_oracle():
+    c = case("colour_small")
+    F = oracle_frames(c)
+    ref = oracle.reconstruct(c["g"], c["rig"], as64(F), as64(c["sig"]), np.zeros(c["em"].shape), 4,
+                             step_vox=STEP, albedo=c["albedo"], background=c["bg"], s_res=c["M"],
+                             n_dirs=c["dirs"])
+    say("reconstruct colour_small sart+scatter")
+    with plan_for(c) as p:
+        x = host(p.reconstruct(dev(F), dev(c["sig"]), dev(np.zeros(c["em"].shape)), 4))
+    for ch in range(3):
+        assert rel_rms(x[ch], ref[ch]) <= VOLUME_RMS
+
+
+def test_warm_start_equals_continued_run():
+    c = case("tiny")
+    F = oracle_frames(c)
+    say("warm start")
+    with plan_for(c) as p:
+        a = p.reconstruct(dev(F), dev(c["sig"]), dev(np.zeros(c["em"].shape)), 2)
+        a = host(p.reconstruct(dev(F), dev(c["sig"]), a, 3))
+        b = host(p.reconstruct(dev(F), dev(c["sig"]), dev(np.zeros(c["em"].shape)), 5))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_determinism_bitwise():
+    c = case("colour_small")
+    F = oracle_frames(c)
+    say("determinism")
+    with plan_for(c) as p:
+        runs = [host(p.reconstruct(dev(F), dev(c["sig"]), dev(np.zeros(c["em"].shape)), 3))
+                for _ in range(2)]
+        y = dev(np.random.default_rng(0).normal(size=F.shape))
+        bps = [host(p.backproject(dev(c["sig"]), y)) for _ in range(2)]
+    np.testing.assert_array_equal(runs[0], runs[1])
+    np.testing.assert_array_equal(bps[0], bps[1])
+
+
+# ---------------------------------------------------------- a7/a8 temperature
+def test_temperature_lut_map_invert_match_oracle():
+    tpo = oracle.TempParams()
+    lut_o = oracle.temp_lut(tpo)
+    g = synth.Grid(10, 9, 8)
+    rig = synth.ring_rig(2, 8, 8)
+    T = f32(np.random.default_rng(2).uniform(800.0, 2300.0, size=g.shape_zyx))
+    em_o, sig_o = oracle.temp_map(tpo, lut_o, as64(T))
+    say("temperature map")
+    with rte().Plan(g, rig, channels=1) as p:
+        lut = p.temperature_lut().astype(np.float64)
+        em, sig = p.temperature_map(dev(T))
+        em, sig = host(em), host(sig)
+        Tinv = host(p.temperature_invert(dev(em_o[1])))
+    np.testing.assert_allclose(lut, lut_o, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(em, em_o, rtol=2e-6, atol=1e-12)
+    np.testing.assert_allclose(sig, sig_o, rtol=2e-6, atol=1e-6)
+    vis = em_o[1] >= 1e-3 * em_o[1].max()
+    np.testing.assert_allclose(Tinv[vis], T[vis], rtol=0, atol=0.05)
+
+
+def temp_case():
+    g, T = synth.temperature_volume(seed=3, n=16, n_blobs=5)
+    rig = synth.ring_rig(6, 32, 32, elevation_jitter_deg=15, seed=3)
+    tpo = oracle.TempParams()
+    lut_o = oracle.temp_lut(tpo)
+    T = f32(T)
+    em, sig = oracle.temp_map(tpo, lut_o, as64(T))
+    F = f32(oracle.render(g, rig, em, sig, step_vox=STEP))
+    return g, rig, T, F, tpo, lut_o
+
+
+def test_temperature_fit_matches_oracle():
+    g, rig, T, F, tpo, lut_o = temp_case()
+    T0 = np.full(g.shape_zyx, 800.0)
+    ref = oracle.temperature_fit(g, rig, tpo, lut_o, as64(F), T0, 30, step_vox=STEP)
+    say("temperature fit")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        Tg = host(p.reconstruct_temperature(dev(F), dev(T0), 30))
+    e_ref, _ = oracle.temp_map(tpo, lut_o, ref)
+    e_gpu, _ = oracle.temp_map(tpo, lut_o, Tg)
+    assert rel_rms(e_gpu[1], e_ref[1]) <= VOLUME_RMS
+    vis = e_ref[1] >= 1e-3 * e_ref[1].max()
+    assert vis.sum() > 50
+    assert np.sqrt(np.mean(((Tg - ref)[vis] / 1400.0) ** 2)) <= VOLUME_RMS
+
+
+def test_temperature_fit_fixed_point_on_gpu():
+    g, rig, T, F, tpo, lut_o = temp_case()
+    say("temperature fixed point")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        em, sig = p.temperature_map(dev(T))
+        F_gpu = p.render(em[1:2].contiguous(), sig)
+        frames = dev(np.zeros((rig.n_views, 3, rig.height, rig.width)))
+        frames[:, 1] = F_gpu[:, 0]
+        Tg = host(p.reconstruct_temperature(frames, dev(T), 30))
+    e_o, _ = oracle.temp_map(tpo, lut_o, as64(T))
+    vis = e_o[1] >= 1e-3 * e_o[1].max()
+    assert np.abs(Tg - T)[vis].max() <= 0.05
+
+
+# ---------------------------------------------------------------- edge cases
+def test_all_rays_miss():
+    g = synth.Grid(8, 8, 8)
+    rig = synth.ring_rig(2, 16, 12)
+    for v, eye in enumerate(rig.centres()):  # turn each camera to face away from the box
+        R, t = synth._look_at(eye, 2 * eye - np.array([0.5, 0.5, 0.5]), np.array([0, 0, 1.0]))
+        rig.R[v], rig.t[v] = R, t
+    tn, tf, K = oracle.ray_table(g, rig)
+    assert K.sum() == 0
+    say("all miss")
+    with rte().Plan(g, rig, channels=1, background=0.25) as p:
+        assert p.samples == 0 and p.hit_rays == 0
+        em = dev(np.ones((1, 8, 8, 8)))
+        sig = dev(np.ones((8, 8, 8)))
+        img = host(p.render(em, sig))
+        d = host(p.backproject(sig, dev(np.ones((2, 1, 12, 16)))))
+        x = host(p.reconstruct(dev(np.ones((2, 1, 12, 16))), sig, em, 3))
+    assert np.all(img == 0.25)
+    assert np.all(d == 0.0)
+    assert np.all(x == 1.0)
+
+
+def test_minimal_grid_and_tiny_images():
+    g = synth.Grid(2, 2, 2)
+    rig = synth.ring_rig(3, 3, 2, radius=2.0, fov_y_deg=30.0, elevation_jitter_deg=10, seed=1)
+    rng = np.random.default_rng(0)
+    em, sig = f32(rng.uniform(size=(1, 2, 2, 2))), f32(rng.uniform(size=(2, 2, 2)))
+    ref = oracle.render(g, rig, as64(em), as64(sig))
+    y = f32(rng.normal(size=ref.shape))
+    bref = oracle.backproject_adjoint(g, rig, as64(sig), as64(y))
+    say("minimal grid")
+    with rte().Plan(g, rig, channels=1) as p:
+        img = host(p.render(dev(em), dev(sig)))
+        d = host(p.backproject(dev(sig), dev(y)))
+    assert render_rel(img, ref) <= RENDER_REL
+    assert rel_max(d, bref) <= BACKPROJ_REL
+
+
+def test_camera_inside_the_volume():
+    """A camera inside the box: rays start at t = 0 and some cells lie behind
+    the camera; the gather falls back to scanning the whole image for cells
+    it cannot project."""
+    g = synth.Grid(9, 9, 9)
+    R, t = synth._look_at(np.array([0.45, 0.5, 0.55]), np.array([1.0, 0.8, 0.3]), np.array([0, 0, 1.0]))
+    rig = synth.Rig(np.array([10.0]), np.array([10.0]), np.array([6.0]), np.array([5.0]), R[None],
+                    t[None], 12, 10)
+    em, sig = blob_volume(g, 1, 3)
+    ref = oracle.render(g, rig, as64(em), as64(sig))
+    y = f32(np.random.default_rng(1).normal(size=ref.shape))
+    bref = oracle.backproject_adjoint(g, rig, as64(sig), as64(y))
+    say("camera inside")
+    with rte().Plan(g, rig, channels=1) as p:
+        img = host(p.render(dev(em), dev(sig)))
+        d = host(p.backproject(dev(sig), dev(y)))
+    assert render_rel(img, ref) <= RENDER_REL
+    assert rel_max(d, bref) <= BACKPROJ_REL
