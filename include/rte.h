@@ -237,7 +237,9 @@ enum {
     RTE_KERNEL_UPDATE = 4,
     RTE_KERNEL_TEMP_MAP = 5,
     RTE_KERNEL_PACK = 6,
-    RTE_KERNEL_COUNT = 7
+    RTE_KERNEL_WEIGHTS = 7, /* render pass that only produces per-sample weights */
+    RTE_KERNEL_COLSUM = 8,  /* gather pass for the column sums A^T 1 */
+    RTE_KERNEL_COUNT = 9
 };
 int rte_plan_set_timing(rte_plan *plan, int32_t enable);
 int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);

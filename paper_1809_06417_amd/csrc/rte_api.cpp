@@ -547,7 +547,7 @@ int rte_backproject(rte_plan *plan, const float *extinction, const float *residu
     const int C = plan->params.channels;
     if (mode == RTE_BP_ADJOINT) {
         RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, nullptr, extinction, C, s));
-        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+        RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
         RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
                    rte::launch_gather(plan, C, rte::kGatherAdjoint, residual, 0.f, 0.f, 0.f, s));
@@ -581,9 +581,9 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
     if (upd != RTE_UPDATE_PAPER && iters > 0) {
         // row sums come out of every render; column sums A^T 1 once per call
-        RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+        RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+        RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
                    rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s));
         RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                    rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
 
 RTE_OK, RTE_ERR_INVALID_ARG, RTE_ERR_BUDGET, RTE_ERR_HIP, RTE_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 KERNELS = {"rays": 0, "render": 1, "inscatter": 2, "gather": 3, "update": 4, "temp_map": 5,
-           "pack": 6}
+           "pack": 6, "weights": 7, "colsum": 8}
 UPDATES = {"sart": 0, "paper": 1, "mlem": 2}
 BP_MODES = {"adjoint": 0, "paper": 1}
 

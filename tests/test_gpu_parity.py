@@ -303,7 +303,7 @@ def test_temperature_lut_map_invert_match_oracle():
 
 
 def temp_case():
-    g, T = synth.temperature_volume(seed=3, n=16, n_blobs=5)
+    g, T = synth.temperature_volume(seed=3, n=20, n_blobs=8)
     rig = synth.ring_rig(6, 32, 32, elevation_jitter_deg=15, seed=3)
     tpo = oracle.TempParams()
     lut_o = oracle.temp_lut(tpo)
