@@ -95,7 +95,7 @@ int validate_config(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
 
 struct Derived {
     int V, W, H, tiles_x, tiles_y, tiles_per_view, n_tiles;
-    int64_t n_rays, n_nodes, n_cells;
+    int64_t n_rays, n_nodes, n_cells, n_part_cells;
     double h[3], ds;
 };
 
@@ -112,6 +112,7 @@ Derived derive(const rte_grid *grid, const rte_camera *cams, int32_t ncams, cons
     d.n_rays = (int64_t)d.V * d.W * d.H;
     d.n_nodes = (int64_t)grid->nx * grid->ny * grid->nz;
     d.n_cells = (int64_t)(grid->nx - 1) * (grid->ny - 1) * (grid->nz - 1);
+    d.n_part_cells = (int64_t)((grid->nx - 1 + 7) / 8) * ((grid->ny - 1 + 7) / 8) * ((grid->nz - 1 + 3) / 4) * 256;
     const int n[3] = {grid->nx, grid->ny, grid->nz};
     double hmin = 1e300;
     for (int i = 0; i < 3; ++i) {
@@ -185,7 +186,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
     s.dirs = sizeof(float4) * kMaxDirs;
     s.y = sizeof(float) * (size_t)d.n_rays * C;
-    s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_cells, 1);
+    s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
     s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.vol + s.scat + s.dirs + s.y +
@@ -388,6 +389,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     p->n_rays = d.n_rays;
     p->n_nodes = d.n_nodes;
     p->n_cells = d.n_cells;
+    p->n_part_cells = d.n_part_cells;
     for (int i = 0; i < 3; ++i) p->h[i] = d.h[i];
     p->ds = d.ds;
     p->last_stream = s;

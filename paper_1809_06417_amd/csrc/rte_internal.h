@@ -48,12 +48,6 @@ struct ViewProj {
     float P[12];
 };
 
-struct GridDev {
-    int nx, ny, nz;
-    float ds;      // march step, world units
-    float inv_ds;
-};
-
 struct TimingRecord {
     int kernel;
     hipEvent_t start, stop;
@@ -69,6 +63,7 @@ struct rte_plan {
     int V = 0, W = 0, H = 0;
     int tiles_x = 0, tiles_y = 0, tiles_per_view = 0, n_tiles = 0;
     int64_t n_rays = 0, n_nodes = 0, n_cells = 0;
+    int64_t n_part_cells = 0;  // cells rounded up to whole 8x8x4 gather bricks
     double h[3] = {0, 0, 0};
     double ds = 0.0;
     uint64_t samples = 0, hit_rays = 0, g_floats = 0;

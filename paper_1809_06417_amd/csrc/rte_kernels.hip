@@ -418,17 +418,22 @@ struct ScatArgs {
     float inv_ndirs;
 };
 
-// 32 lanes per node (lane l takes directions l, l+32, ...), 8 nodes per
-// block; the 32 partial sums are combined by a fixed xor butterfly and lane 0
-// of each group stores the node value.
+// A block owns a 4x4x4 brick of in-scatter nodes and kScatGroups waves; wave
+// w marches directions w, w + kScatGroups, ... from all 64 nodes of the brick,
+// so the 64 rays of a wave are parallel and neighbouring (coherent gathers).
+// The per-wave partial sums are added in wave order through LDS.
+constexpr int kScatGroups = 8;
+
 template <int C>
-__global__ __launch_bounds__(kBlock) void inscatter_kernel(ScatArgs a)
+__global__ __launch_bounds__(64 * kScatGroups) void inscatter_kernel(ScatArgs a)
 {
-    const int grp = threadIdx.x >> 5, l = threadIdx.x & 31;
-    const int M = a.M;
-    const int m = blockIdx.x * 8 + grp;
-    if (m >= M * M * M) return;  // whole 32-lane group leaves together
-    const int mx = m % M, my = (m / M) % M, mz = m / (M * M);
+    __shared__ float red[kScatGroups][64][C];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int M = a.M, bm = (M + 3) >> 2;
+    const int b = blockIdx.x;
+    const int bx = b % bm, by = (b / bm) % bm, bz = b / (bm * bm);
+    const int mx = bx * 4 + (l & 3), my = by * 4 + ((l >> 2) & 3), mz = bz * 4 + (l >> 4);
+    const bool valid = mx < M && my < M && mz < M;
     const float px = (float)mx * a.p_scale[0], py = (float)my * a.p_scale[1],
                 pz = (float)mz * a.p_scale[2];
     const float tx = (float)(a.nx - 1), ty = (float)(a.ny - 1), tz = (float)(a.nz - 1);
@@ -437,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void inscatter_kernel(ScatArgs a)
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    for (int d = l; d < a.ndirs; d += 32) {
+    for (int d = w; valid && d < a.ndirs; d += kScatGroups) {
         const float4 u = a.dirs[d];
         // exit distance from an interior point (world units)
         float ell = INFINITY;
@@ -458,10 +463,10 @@ __global__ __launch_bounds__(kBlock) void inscatter_kernel(ScatArgs a)
             cell_of(fmaf(s, u.x, px), a.nx, ix, fx);
             cell_of(fmaf(s, u.y, py), a.ny, iy, fy);
             cell_of(fmaf(s, u.z, pz), a.nz, iz, fz);
-            float w[8];
-            tri_weights(fx, fy, fz, w);
+            float wt[8];
+            tri_weights(fx, fy, fz, wt);
             float em[C], sig;
-            sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, w, em, sig);
+            sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, wt, em, sig);
             sig = fmaxf(sig, 0.0f);
             float e;
             const float wg = T * len * phi_exp(sig * len, e);
@@ -471,23 +476,29 @@ __global__ __launch_bounds__(kBlock) void inscatter_kernel(ScatArgs a)
         }
     }
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1)
+    for (int c = 0; c < C; ++c) red[w][l][c] = acc[c];
+    __syncthreads();
+    if (w != 0 || !valid) return;
+    float tot[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off, 32);
-    if (l == 0) {
-        float4 o = make_float4(acc[0] * a.inv_ndirs, 0.f, 0.f, 0.f);
+    for (int c = 0; c < C; ++c) {
+        tot[c] = 0.0f;
+        for (int g = 0; g < kScatGroups; ++g) tot[c] += red[g][l][c];
+        tot[c] *= a.inv_ndirs;
+    }
+    const int m = (mz * M + my) * M + mx;
+    float4 o = make_float4(tot[0], 0.f, 0.f, 0.f);
+    if constexpr (C == 3) {
+        o.y = tot[1];
+        o.z = tot[2];
+    }
+    a.scat[m] = o;
+    if (a.planar) {
+        const int m3 = M * M * M;
+        a.planar[m] = o.x;
         if constexpr (C == 3) {
-            o.y = acc[1] * a.inv_ndirs;
-            o.z = acc[2] * a.inv_ndirs;
-        }
-        a.scat[m] = o;
-        if (a.planar) {
-            const int m3 = M * M * M;
-            a.planar[m] = o.x;
-            if constexpr (C == 3) {
-                a.planar[m3 + m] = o.y;
-                a.planar[2 * m3 + m] = o.z;
-            }
+            a.planar[m3 + m] = o.y;
+            a.planar[2 * m3 + m] = o.z;
         }
     }
 }
@@ -598,8 +609,12 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                     }
                 }
                 if (!(s_out >= s_in)) continue;
-                const int k_lo = max(0, (int)floorf(fmaf(s_in, a.inv_ds, -0.5f)));
-                const int k_hi = min(K - 1, (int)ceilf(fmaf(s_out, a.inv_ds, -0.5f)));
+                // samples k < K-1 sit at s = (k + 1/2) ds; the last one lies in
+                // [(K-1) ds, L]. The padded box keeps every sample the render
+                // placed in this cell inside [s_in, s_out] despite rounding.
+                const int k_lo = max(0, (int)ceilf(fmaf(s_in, a.inv_ds, -0.5f)));
+                int k_hi = min(K - 2, (int)floorf(fmaf(s_out, a.inv_ds, -0.5f)));
+                if (s_out >= (float)(K - 1) * a.ds) k_hi = K - 1;
                 if (k_lo > k_hi) continue;
                 float yv[C];
                 if constexpr (MODE != kGatherCols) {
@@ -653,7 +668,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
             }
         }
     }
-    const int cell = (cz * (a.ny - 1) + cy) * (a.nx - 1) + cx;
+    // brick-major cell index: a wave stores 64 consecutive floats per plane
+    const int cell = b * kBlock + threadIdx.x;
 #pragma unroll
     for (int c = 0; c < 8; ++c)
 #pragma unroll
@@ -672,6 +688,7 @@ struct UpdateArgs {
     int lut_cap, lut_size, fit_channel;
     float t_min, t_max;
     int nx, ny, nz, ncells, acc;
+    int bx, by;  // gather bricks (8 x 8 x 4 cells) along x and y
     int64_t n;
     float lambda;
     int clamp_nonneg;
@@ -708,7 +725,8 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
     for (int e = 0; e < 8; ++e) {
         const int cx = jx - (e & 1), cy = jy - ((e >> 1) & 1), cz = jz - ((e >> 2) & 1);
         if (cx < 0 || cy < 0 || cz < 0 || cx > a.nx - 2 || cy > a.ny - 2 || cz > a.nz - 2) continue;
-        const int cell = (cz * (a.ny - 1) + cy) * (a.nx - 1) + cx;
+        const int brick = ((cz >> 2) * a.by + (cy >> 3)) * a.bx + (cx >> 3);
+        const int cell = brick * kBlock + (((cz & 3) * 8 + (cy & 7)) * 8 + (cx & 7));
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sum[q] += a.part[(int64_t)(e * a.acc + q) * a.ncells + cell];
     }
@@ -961,12 +979,12 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     }
     a.ds = (float)(p->params.scatter_step * hs_min);
     a.inv_ndirs = 1.0f / (float)a.ndirs;
-    const int64_t m3 = (int64_t)a.M * a.M * a.M;
-    const int nb = (int)((m3 + 7) / 8);
+    const int bm = (a.M + 3) / 4;
+    const int nb = bm * bm * bm;
     if (p->params.channels == 3)
-        hipLaunchKernelGGL(inscatter_kernel<3>, dim3(nb), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(inscatter_kernel<3>, dim3(nb), dim3(64 * kScatGroups), 0, s, a);
     else
-        hipLaunchKernelGGL(inscatter_kernel<1>, dim3(nb), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(inscatter_kernel<1>, dim3(nb), dim3(64 * kScatGroups), 0, s, a);
     return hipGetLastError();
 }
 
@@ -999,7 +1017,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
     a.by = (a.ny - 1 + 7) / 8;
     a.bz = (a.nz - 1 + 3) / 4;
     a.nb8 = grid8((int64_t)a.bx * a.by * a.bz);
-    a.ncells = (int)p->n_cells;
+    a.ncells = (int)p->n_part_cells;
     a.ds = (float)p->ds;
     a.inv_ds = (float)(1.0 / p->ds);
     a.alpha_l = alpha_l;
@@ -1050,7 +1068,9 @@ hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, flo
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
     a.nz = p->grid.nz;
-    a.ncells = (int)p->n_cells;
+    a.ncells = (int)p->n_part_cells;
+    a.bx = (p->grid.nx - 1 + 7) / 8;
+    a.by = (p->grid.ny - 1 + 7) / 8;
     a.acc = acc;
     a.n = p->n_nodes;
     a.lambda = lambda;
