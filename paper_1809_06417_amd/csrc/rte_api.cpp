@@ -56,8 +56,9 @@ int validate_config(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
             !(grid->bbox_max[i] > grid->bbox_min[i]))
             return fail(RTE_ERR_INVALID_ARG, "bbox axis %d is empty or not finite", i);
     const int64_t nodes = (int64_t)grid->nx * grid->ny * grid->nz;
-    if (nodes >= (int64_t(1) << 31) / 4)
-        return fail(RTE_ERR_INVALID_ARG, "grid too large (%lld key points)", (long long)nodes);
+    if (nodes >= (int64_t(1) << 27) || (int64_t)grid->nx * grid->ny >= (int64_t(1) << 24))
+        return fail(RTE_ERR_INVALID_ARG, "grid too large (%lld key points; limits: 2^27 key points, nx*ny < 2^24)",
+                    (long long)nodes);
     if (ncams < 1) return fail(RTE_ERR_INVALID_ARG, "need at least one camera");
     const int W = cams[0].width, H = cams[0].height;
     if (W < 1 || H < 1) return fail(RTE_ERR_INVALID_ARG, "camera 0 has an empty image");
@@ -180,7 +181,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.proj = sizeof(rte::ViewProj) * d.V;
     s.rays = 2 * sizeof(float4) * d.n_rays;
     s.tnear = sizeof(float) * d.n_rays;
-    s.tiles = (sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
+    s.tiles = (2 * sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
     s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
     s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
@@ -280,7 +281,7 @@ void free_plan(rte_plan *p)
     }
     for (auto e : p->event_pool) hipEventDestroy(e);
     void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
-                    p->d_tile_off, p->d_g, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
+                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
                     p->d_cols, p->d_lut};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -433,8 +434,19 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         g += (uint64_t)kmax[t] * rte::kTileRays;
     }
     p->g_floats = g;
-    if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint64_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess)
-        return bail(fail(RTE_ERR_HIP, "tile offsets upload failed"));
+    // launch order of the render: tiles that hold samples, longest march first
+    // (stable, so equal tiles keep their spatial order)
+    std::vector<int32_t> order;
+    for (int t = 0; t < d.n_tiles; ++t)
+        if (kmax[t] > 0) order.push_back(t);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return kmax[a] > kmax[b]; });
+    p->n_active_tiles = (int)order.size();
+    if ((rc = dev_alloc(&p->d_tile_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1), acc)))
+        return bail(rc);
+    if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint64_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (!order.empty() && hipMemcpyAsync(p->d_tile_order, order.data(), sizeof(int32_t) * order.size(),
+                                          hipMemcpyHostToDevice, s) != hipSuccess))
+        return bail(fail(RTE_ERR_HIP, "tile tables upload failed"));
 
     // remaining workspaces
     const Sizes full = workspace(params, d, g);

@@ -86,8 +86,64 @@ __device__ __forceinline__ float phi_exp(float x, float &e)
                              1.0f / 6.0f),
                   -0.5f),
              1.0f);
-    const float dir = __fdividef(1.0f - e, x);
+    const float dir = (1.0f - e) * __builtin_amdgcn_rcpf(x);
     return x < 0.25f ? ser : dir;
+}
+
+// Raw buffer resource over [p, p + bytes): loads take a 32-bit lane offset
+// plus a uniform (SGPR) offset, and the hardware returns 0 for any access
+// outside the range instead of touching other memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int64_t bytes)
+{
+    const int n = bytes > 0x7fffffff ? 0x7fffffff : (int)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, n, 0x00020000);
+}
+
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    using u4 = unsigned int __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                       __uint_as_float(v.w));
+}
+
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    using u2 = unsigned int __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
+// Trilinear sample of a packed volume through a buffer resource: coff holds
+// the byte offsets of the 8 cell corners (uniform across the launch).
+template <int C>
+__device__ __forceinline__ void sample_volume_rsrc(__amdgpu_buffer_rsrc_t r, const int coff[8], int base_bytes,
+                                                   const float w[8], float em[C], float &sig)
+{
+    sig = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) em[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if constexpr (C == 3) {
+            const float4 v = bload4(r, base_bytes, coff[c]);
+            em[0] = fmaf(w[c], v.x, em[0]);
+            em[1] = fmaf(w[c], v.y, em[1]);
+            em[2] = fmaf(w[c], v.z, em[2]);
+            sig = fmaf(w[c], v.w, sig);
+        } else {
+            const float2 v = bload2(r, base_bytes, coff[c]);
+            em[0] = fmaf(w[c], v.x, em[0]);
+            sig = fmaf(w[c], v.y, sig);
+        }
+    }
+}
+
+__device__ __forceinline__ void corner_offsets(int nx, int nxy, int elem, int coff[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        coff[c] = ((c & 1) + ((c >> 1) & 1) * nx + ((c >> 2) & 1) * nxy) * elem;
 }
 
 template <int C> struct Packed;
@@ -290,6 +346,8 @@ __global__ __launch_bounds__(kBlock) void pack_scatter_kernel(const float *plana
 struct RenderArgs {
     const float4 *rayA, *rayB;
     const uint64_t *tile_off;
+    const int32_t *tile_order;  // active tiles, heaviest first
+    int n_active;
     const float *vol;
     const float4 *scat;
     const float *frames;
@@ -303,14 +361,18 @@ struct RenderArgs {
 };
 
 // One work-item per pixel ray; a block holds four 8x8 tiles (one per wave).
+// Only tiles that some ray of the volume crosses are launched, heaviest
+// (largest segment count) first, so the long marches start early and the
+// short ones fill the tail.
 // EMIS: read the emission (false: weights only). SCAT: add in-scattering.
 // WRITE_G: store the per-sample weight g_k = T_k Delta_k phi_k.
 template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
 __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = xcd_remap(blockIdx.x, a.nb8) * 4 + wave;
-    if (tile >= a.n_tiles) return;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.n_active) return;
+    const int tile = a.tile_order[slot];
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
@@ -320,8 +382,15 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
     const int r = v * HW + pix;
     const float4 A = a.rayA[r], B = a.rayB[r];
     const int K = __float_as_int(B.w);
-    const auto *vol = reinterpret_cast<const typename Packed<C>::T *>(a.vol);
-    const int nxy = a.nx * a.ny;
+    const int nx = a.nx, nxy = a.nx * a.ny;
+    constexpr int elem = C == 3 ? 16 : 8;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(a.vol, (int64_t)nxy * a.nz * elem);
+    int coff[8];
+    corner_offsets(nx, nxy, elem, coff);
+    const int M = a.M, MM = a.M * a.M;
+    const __amdgpu_buffer_rsrc_t sr = make_rsrc(a.scat, SCAT ? (int64_t)MM * M * 16 : 16);
+    int soff[8];
+    corner_offsets(M, MM, 16, soff);
     float I[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) I[c] = 0.0f;
@@ -340,23 +409,22 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
         float w[8];
         tri_weights(fx, fy, fz, w);
         float em[C], sig;
-        sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, w, em, sig);
+        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
+        sample_volume_rsrc<C>(vr, coff, base * elem, w, em, sig);
         sig = fmaxf(sig, 0.0f);
         if constexpr (SCAT) {
             int jx, jy, jz;
             float gx, gy, gz;
-            cell_of(x * a.s_scale[0], a.M, jx, gx);
-            cell_of(y * a.s_scale[1], a.M, jy, gy);
-            cell_of(z * a.s_scale[2], a.M, jz, gz);
+            cell_of(x * a.s_scale[0], M, jx, gx);
+            cell_of(y * a.s_scale[1], M, jy, gy);
+            cell_of(z * a.s_scale[2], M, jz, gz);
             float ws[8];
             tri_weights(gx, gy, gz, ws);
-            const int M = a.M, MM = a.M * a.M;
-            const int base = jz * MM + jy * M + jx;
-            const int off[8] = {0, 1, M, M + 1, MM, MM + 1, MM + M, MM + M + 1};
+            const int sb = ((int)(__umul24(jz, MM) + __umul24(jy, M)) + jx) * 16;
             float S[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const float4 q = a.scat[base + off[c]];
+                const float4 q = bload4(sr, sb, soff[c]);
                 S[0] = fmaf(ws[c], q.x, S[0]);
                 S[1] = fmaf(ws[c], q.y, S[1]);
                 S[2] = fmaf(ws[c], q.z, S[2]);
@@ -422,7 +490,10 @@ struct ScatArgs {
 // w marches directions w, w + kScatGroups, ... from all 64 nodes of the brick,
 // so the 64 rays of a wave are parallel and neighbouring (coherent gathers).
 // The per-wave partial sums are added in wave order through LDS.
-constexpr int kScatGroups = 8;
+#ifndef RTE_SCAT_GROUPS
+#define RTE_SCAT_GROUPS 8
+#endif
+constexpr int kScatGroups = RTE_SCAT_GROUPS;
 
 template <int C>
 __global__ __launch_bounds__(64 * kScatGroups) void inscatter_kernel(ScatArgs a)
@@ -592,9 +663,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                 const int pix = py * a.W + px;
                 const int r = v * HW + pix;
                 const float4 B = a.rayB[r];
+                const float4 A = a.rayA[r];
                 const int K = __float_as_int(B.w);
                 if (K == 0) continue;
-                const float4 A = a.rayA[r];
                 // slab test against the padded cell box, in ray offset s
                 float s_in = 0.0f, s_out = A.w;
                 {
@@ -895,7 +966,8 @@ hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream
 template <int C, bool EMIS, bool SCAT, bool WG, int EPI>
 static void render_launch(const RenderArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((render_kernel<C, EMIS, SCAT, WG, EPI>), dim3(a.nb8), dim3(kBlock), 0, s, a);
+    if (a.nb8 > 0)
+        hipLaunchKernelGGL((render_kernel<C, EMIS, SCAT, WG, EPI>), dim3(a.nb8), dim3(kBlock), 0, s, a);
 }
 
 template <int C>
@@ -943,7 +1015,9 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
     a.tiles_x = p->tiles_x;
     a.tiles_per_view = p->tiles_per_view;
     a.n_tiles = p->n_tiles;
-    a.nb8 = grid8((p->n_tiles + 3) / 4);
+    a.tile_order = p->d_tile_order;
+    a.n_active = p->n_active_tiles;
+    a.nb8 = (p->n_active_tiles + 3) / 4;
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
     a.nz = p->grid.nz;
