@@ -435,12 +435,15 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     }
     p->g_floats = g;
     // launch order of the render: tiles that hold samples, longest march first
-    // (stable, so equal tiles keep their spatial order)
+    // (stable, so equal tiles keep their spatial order); tiles without
+    // samples follow, they only receive the background in image renders
     std::vector<int32_t> order;
     for (int t = 0; t < d.n_tiles; ++t)
         if (kmax[t] > 0) order.push_back(t);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return kmax[a] > kmax[b]; });
     p->n_active_tiles = (int)order.size();
+    for (int t = 0; t < d.n_tiles; ++t)
+        if (kmax[t] == 0) order.push_back(t);
     if ((rc = dev_alloc(&p->d_tile_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1), acc)))
         return bail(rc);
     if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint64_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -77,7 +77,7 @@ struct rte_plan {
     float *d_tnear = nullptr;       // entry distance (export only)
     int32_t *d_tile_kmax = nullptr;
     uint64_t *d_tile_off = nullptr;
-    int32_t *d_tile_order = nullptr; // tiles with rays through the volume, heaviest first
+    int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
     int n_active_tiles = 0;
     float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)

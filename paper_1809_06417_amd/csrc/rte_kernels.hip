@@ -346,8 +346,8 @@ __global__ __launch_bounds__(kBlock) void pack_scatter_kernel(const float *plana
 struct RenderArgs {
     const float4 *rayA, *rayB;
     const uint64_t *tile_off;
-    const int32_t *tile_order;  // active tiles, heaviest first
-    int n_active;
+    const int32_t *tile_order;  // tiles with samples (heaviest first), then empty tiles
+    int n_launch;               // leading entries of tile_order this launch covers
     const float *vol;
     const float4 *scat;
     const float *frames;
@@ -361,9 +361,10 @@ struct RenderArgs {
 };
 
 // One work-item per pixel ray; a block holds four 8x8 tiles (one per wave).
-// Only tiles that some ray of the volume crosses are launched, heaviest
-// (largest segment count) first, so the long marches start early and the
-// short ones fill the tail.
+// Tiles are taken in plan order: tiles that some ray of the volume crosses,
+// heaviest (largest segment count) first, so the long marches start early
+// and the short ones fill the tail; empty tiles come last and are launched
+// only when an image (background for misses) is written.
 // EMIS: read the emission (false: weights only). SCAT: add in-scattering.
 // WRITE_G: store the per-sample weight g_k = T_k Delta_k phi_k.
 template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + wave;
-    if (slot >= a.n_active) return;
+    if (slot >= a.n_launch) return;
     const int tile = a.tile_order[slot];
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
@@ -1016,8 +1017,10 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
     a.tiles_per_view = p->tiles_per_view;
     a.n_tiles = p->n_tiles;
     a.tile_order = p->d_tile_order;
-    a.n_active = p->n_active_tiles;
-    a.nb8 = (p->n_active_tiles + 3) / 4;
+    // an image needs every pixel (misses get the background); residuals and
+    // weights are only ever read for rays that hold samples
+    a.n_launch = epilogue == kEpiImage ? p->n_tiles : p->n_active_tiles;
+    a.nb8 = (a.n_launch + 3) / 4;
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
     a.nz = p->grid.nz;
