@@ -69,7 +69,9 @@ typedef struct {
  *  background    radiance behind the volume (0: dark capture, Sec. 4.1).
  *  scatter_res   nodes per axis of the in-scatter grid (>= 2 when albedo > 0).
  *  scatter_dirs  directions of the isotropic in-scatter average (1..256).
- *  scatter_step  in-scatter march step in units of the in-scatter node spacing. */
+ *  scatter_step  in-scatter march step in units of the in-scatter node spacing.
+ *  flags         RTE_PLAN_* bits (RTE_PLAN_GRADIENTS: also allocate what
+ *                rte_render_backward needs). */
 typedef struct {
     int32_t channels;
     float step_vox;
@@ -78,7 +80,10 @@ typedef struct {
     int32_t scatter_res;
     int32_t scatter_dirs;
     float scatter_step;
+    int32_t flags;
 } rte_render_params;
+
+#define RTE_PLAN_GRADIENTS 1
 
 /* Back-projection weights. */
 typedef enum {
@@ -167,6 +172,31 @@ int rte_ray_table(rte_plan *plan, float *t_near, float *t_far, int32_t *nseg, vo
 int rte_render(rte_plan *plan, const float *emission, const float *extinction,
                const float *inscatter, float *images, void *stream);
 
+/* rte_render that also writes the transmittance left at each ray's exit,
+ * exit_transmittance [V][H][W] (what rte_render_backward needs to re-march
+ * each ray backwards). */
+int rte_render_forward(rte_plan *plan, const float *emission, const float *extinction,
+                       const float *inscatter, float *images, float *exit_transmittance,
+                       void *stream);
+
+/* Gradient of a scalar loss through the render of Eq. 5-8, given dL/dI.
+ * For every ray a reverse march recovers the transmittance in front of each
+ * sample from exit_transmittance (T_k = T_{k+1} e^{sigma_k Delta_k}; no
+ * per-sample state is kept from the forward pass) and forms
+ *   dI_c/d eps_k   = T_k Delta_k phi_k,
+ *   dI_c/d sigma_k = T_k (albedo S_c Delta_k phi_k + j_c Delta_k^2 phi'_k)
+ *                    - Delta_k (radiance behind sample k);
+ * these reach the key points through the trilinear weights in an
+ * atomics-free voxel-owned gather. The in-scatter grid is held fixed.
+ * Needs a plan created with RTE_PLAN_GRADIENTS. emission [C][nz][ny][nx],
+ * extinction [nz][ny][nx], inscatter as in rte_render, exit_transmittance
+ * from rte_render_forward on the same inputs, grad_images [V][C][H][W];
+ * writes grad_emission [C][nz][ny][nx] and grad_extinction [nz][ny][nx]. */
+int rte_render_backward(rte_plan *plan, const float *emission, const float *extinction,
+                        const float *inscatter, const float *exit_transmittance,
+                        const float *grad_images, float *grad_emission, float *grad_extinction,
+                        void *stream);
+
 /* In-scattered radiance grid (Eq. 5 third term, isotropic phase function of
  * Eq. 9 at g = 0): at each node p of an M^3 grid over the box, the mean over
  * scatter_dirs spherical-Fibonacci directions u of the emission-absorption
@@ -239,7 +269,8 @@ enum {
     RTE_KERNEL_PACK = 6,
     RTE_KERNEL_WEIGHTS = 7, /* render pass that only produces per-sample weights */
     RTE_KERNEL_COLSUM = 8,  /* gather pass for the column sums A^T 1 */
-    RTE_KERNEL_COUNT = 9
+    RTE_KERNEL_ADJOINT = 9, /* reverse march of rte_render_backward */
+    RTE_KERNEL_COUNT = 10
 };
 int rte_plan_set_timing(rte_plan *plan, int32_t enable);
 int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);

@@ -14,7 +14,7 @@ import numpy as np
 __all__ = [
     "lib", "ray_table", "render", "inscatter", "backproject_adjoint", "backproject_paper",
     "reconstruct", "planck", "band_radiance", "TempParams", "temp_lut", "temp_map",
-    "temp_invert", "temperature_fit", "num_threads",
+    "temp_invert", "temperature_fit", "num_threads", "render_grad",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +56,8 @@ def lib():
         _lib.orc_backproject_paper.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, d, dp, dp]
         _lib.orc_reconstruct.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d, dp,
                                          dp, dp, i32, i32, d, i32, d, d, d, dp]
+        _lib.orc_render_grad.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, dp, dp, i32, dp,
+                                         dp, dp, dp]
         _lib.orc_planck.argtypes = [d, d]
         _lib.orc_planck.restype = d
         _lib.orc_band_radiance.argtypes = [d, d, d, i32]
@@ -134,6 +136,23 @@ def render(grid, rig, emission, extinction, *, step_vox=0.5, albedo=0.0, backgro
                             _dp(S) if S is not None else None, _dp(img),
                             _dp(rs) if rs is not None else None), "render")
     return (img, rs) if rowsum else img
+
+
+def render_grad(grid, rig, emission, extinction, dLdI, *, step_vox=0.5, albedo=0.0,
+                background=0.0, inscatter=None):
+    """Gradients (d_emission [C,nz,ny,nx], d_extinction [nz,ny,nx]) of a loss with
+    dL/dI = dLdI through the render (in-scatter grid held fixed)."""
+    em = _f64(emission)
+    C = em.shape[0]
+    S = None if inscatter is None else _f64(inscatter)
+    s_res = 0 if S is None else S.shape[-1]
+    d_em = np.zeros(em.shape)
+    d_sig = np.zeros(em.shape[1:])
+    _check(lib().orc_render_grad(ct.byref(_grid(grid)), _cams(rig), rig.n_views, C,
+                                 float(step_vox), float(albedo), float(background), _dp(em),
+                                 _dp(_f64(extinction)), s_res, _dp(S) if S is not None else None,
+                                 _dp(_f64(dLdI)), _dp(d_em), _dp(d_sig)), "render_grad")
+    return d_em, d_sig
 
 
 def inscatter(grid, emission, extinction, *, s_res=32, n_dirs=32, s_step=0.5):

@@ -83,6 +83,7 @@ int validate_config(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
         return fail(RTE_ERR_INVALID_ARG, "albedo must be >= 0");
     if (!std::isfinite(params->background))
         return fail(RTE_ERR_INVALID_ARG, "background must be finite");
+    if (params->flags & ~RTE_PLAN_GRADIENTS) return fail(RTE_ERR_INVALID_ARG, "unknown plan flags 0x%x", params->flags);
     if (params->albedo > 0.0f || params->scatter_res != 0) {
         if (params->scatter_res < 2 || params->scatter_res > 1024)
             return fail(RTE_ERR_INVALID_ARG, "scatter_res must be in [2, 1024] with albedo > 0");
@@ -166,7 +167,7 @@ std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, co
 }
 
 struct Sizes {
-    size_t cams, proj, rays, tnear, tiles, g, vol, scat, dirs, y, part, cols, lut, total;
+    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, dirs, y, part, cols, lut, total;
     int part_acc, lut_cap;
 };
 
@@ -175,7 +176,8 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     Sizes s{};
     const int C = params->channels;
     const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
-    s.part_acc = std::max(C, 2);
+    const bool grads = (params->flags & RTE_PLAN_GRADIENTS) != 0;
+    s.part_acc = std::max(grads ? C + 1 : C, 2);
     s.lut_cap = kMaxLut;
     s.cams = sizeof(rte_camera) * d.V;
     s.proj = sizeof(rte::ViewProj) * d.V;
@@ -183,6 +185,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.tnear = sizeof(float) * d.n_rays;
     s.tiles = (2 * sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
     s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
+    s.q = grads ? s.g : 0;
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
     s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
     s.dirs = sizeof(float4) * kMaxDirs;
@@ -190,7 +193,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
-    s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.vol + s.scat + s.dirs + s.y +
+    s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.dirs + s.y +
               s.part + s.cols + s.lut;
     return s;
 }
@@ -281,7 +284,7 @@ void free_plan(rte_plan *p)
     }
     for (auto e : p->event_pool) hipEventDestroy(e);
     void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
-                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
+                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
                     p->d_cols, p->d_lut};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -456,7 +459,8 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
     p->part_acc = full.part_acc;
     p->lut_cap = full.lut_cap;
-    if ((rc = dev_alloc(&p->d_g, full.g, acc)) || (rc = dev_alloc(&p->d_vol, full.vol, acc)) ||
+    if ((rc = dev_alloc(&p->d_g, full.g, acc)) || (full.q && (rc = dev_alloc(&p->d_q, full.q, acc))) ||
+        (rc = dev_alloc(&p->d_vol, full.vol, acc)) ||
         (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
         (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
         (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)))
@@ -532,6 +536,48 @@ int rte_render(rte_plan *plan, const float *emission, const float *extinction, c
     if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
     RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
                rte::launch_render(plan, C, true, scat, false, rte::kEpiImage, nullptr, C, 0, images, s));
+    return ok();
+}
+
+int rte_render_forward(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
+                       float *images, float *exit_transmittance, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!emission || !extinction || !images || !exit_transmittance)
+        return fail(RTE_ERR_INVALID_ARG, "null emission, extinction, images or exit transmittance");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    const bool scat = inscatter && plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+               rte::launch_render(plan, C, true, scat, false, rte::kEpiImage, nullptr, C, 0, images, s,
+                                  exit_transmittance));
+    return ok();
+}
+
+int rte_render_backward(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
+                        const float *exit_transmittance, const float *grad_images, float *grad_emission,
+                        float *grad_extinction, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!(plan->params.flags & RTE_PLAN_GRADIENTS) || !plan->d_q)
+        return fail(RTE_ERR_UNSUPPORTED, "plan was created without RTE_PLAN_GRADIENTS");
+    if (!emission || !extinction || !exit_transmittance || !grad_images || !grad_emission || !grad_extinction)
+        return fail(RTE_ERR_INVALID_ARG, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    const bool scat = inscatter && plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_ADJOINT, s, rte::launch_adjoint_march(plan, scat, exit_transmittance, grad_images, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+               rte::launch_gather(plan, C, rte::kGatherGrad, grad_images, 0.f, 0.f, 0.f, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+               rte::launch_update(plan, C, C + 1, rte::kUpdGrad, 0.f, 0, grad_emission, nullptr, 0, 0, s,
+                                  grad_extinction));
     return ok();
 }
 

@@ -31,6 +31,7 @@ enum GatherMode : int {
     kGatherAdjointCols = 1,   // acc_c += g * y_c * w ; acc_C += g * w
     kGatherCols = 2,          // acc_0 += g * w
     kGatherPaper = 3,         // acc_c += alpha_l y_c (1-tau)^k exp(-alpha_d D)
+    kGatherGrad = 4,          // acc_c += g * y_c * w ; acc_C += q * w
 };
 
 enum UpdateMode : int {
@@ -40,6 +41,7 @@ enum UpdateMode : int {
     kUpdMlem = 3,    // e *= 1 + lambda (sum / cols - 1) (cols > 0)
     kUpdPaper = 4,   // e += sum
     kUpdTemp = 5,    // EM on the fitted channel, clamp to LUT, invert to T
+    kUpdGrad = 6,    // out[c][j] = sum_c, out2[j] = sum_C (emission / extinction gradients)
 };
 
 // Per-view projection from voxel coordinates to homogeneous pixel
@@ -80,6 +82,7 @@ struct rte_plan {
     int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
     int n_active_tiles = 0;
     float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]
+    float *d_q = nullptr;           // per-sample extinction sensitivities (gradient plans), same layout
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)
     float4 *d_scat = nullptr;       // packed in-scatter grid (rgb, 0)
     float4 *d_dirs = nullptr;       // in-scatter directions, voxel units per world unit
@@ -117,13 +120,15 @@ hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipSt
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s);
+                         int frame_channel0, float *out, hipStream_t s, float *exit_T = nullptr);
+hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
+                                hipStream_t s);
 hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,
                          float alpha_l, float alpha_d, float tau, hipStream_t s);
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s);
+                         int fit_channel, hipStream_t s, float *out2 = nullptr);
 hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, float *sig_planar,
                            bool packed, int lut_size, int fit_channel, float sigma_max,
                            float soot_t0, float soot_span, float t_min, float t_max,

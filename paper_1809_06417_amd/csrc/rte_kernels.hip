@@ -353,6 +353,7 @@ struct RenderArgs {
     const float *frames;
     float *out;
     float *g;
+    float *exit_T;  // optional [V][H][W] transmittance at the exit (image renders)
     int fC, fc0;  // frames hold fC channels; channel c of the render reads fc0 + c
     int W, H, tiles_x, tiles_per_view, n_tiles, nb8;
     int nx, ny, nz, M;
@@ -448,6 +449,7 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
     if constexpr (EPI == kEpiImage) {
 #pragma unroll
         for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
+        if (a.exit_T) a.exit_T[r] = T;
     } else if constexpr (EPI == kEpiSart) {
         const float inv = Rsum > 0.0f ? 1.0f / Rsum : 0.0f;
 #pragma unroll
@@ -471,6 +473,133 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
             const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
             a.out[i] = F - fmaf(T, a.background, I[c]);
         }
+    }
+}
+
+// --------------------------------------------------------- K6 adjoint march
+
+// dphi/dx = (e^-x (1 + x) - 1) / x^2 given e = e^-x; Taylor series below 0.25.
+__device__ __forceinline__ float dphi_f(float x, float e)
+{
+    const float ser =
+        fmaf(x, fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 840.0f, -1.0f / 144.0f), 1.0f / 30.0f), -0.125f),
+                  1.0f / 3.0f),
+             -0.5f);
+    const float dir = (fmaf(e, x, e) - 1.0f) * __builtin_amdgcn_rcpf(x * x);
+    return x < 0.25f ? ser : dir;
+}
+
+struct GradArgs {
+    const float4 *rayA, *rayB;
+    const uint64_t *tile_off;
+    const int32_t *tile_order;
+    int n_launch;
+    const float *vol;
+    const float4 *scat;
+    const float *exit_T;  // [V][H][W]
+    const float *dI;      // dL/dI [V][C][H][W]
+    float *g, *q;         // per-sample outputs, [tile][k][lane]
+    int W, H, tiles_x, tiles_per_view;
+    int nx, ny, nz, M;
+    float ds, albedo, background;
+    float s_scale[3];
+};
+
+// Reverse march of one pixel ray for the gradient of a loss with dL/dI given.
+// Starting from the stored exit transmittance T_K, each step recovers
+// T_k = T_{k+1} e^{a_k}, re-samples the volume, and writes
+//   g_k = T_k Delta_k phi(a_k)                              (dI/d eps_k)
+//   q_k = sum_c dL/dI_c [T_k (albedo S_c Delta_k phi + j_c Delta_k^2 phi')
+//                        - Delta_k R_c]                      (dL/d sigma_k)
+// with R_c the radiance of everything behind sample k; nothing per sample is
+// kept from the forward pass. sigma_k = max(0, trilinear) passes the
+// derivative where the trilinear value is >= 0.
+template <int C, bool SCAT>
+__global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.n_launch) return;
+    const int tile = a.tile_order[slot];
+    const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    if (px >= a.W || py >= a.H) return;
+    const int HW = a.W * a.H;
+    const int pix = py * a.W + px;
+    const int r = v * HW + pix;
+    const float4 A = a.rayA[r], B = a.rayB[r];
+    const int K = __float_as_int(B.w);
+    if (K == 0) return;
+    const int nx = a.nx, nxy = a.nx * a.ny;
+    constexpr int elem = C == 3 ? 16 : 8;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(a.vol, (int64_t)nxy * a.nz * elem);
+    int coff[8];
+    corner_offsets(nx, nxy, elem, coff);
+    const int M = a.M, MM = a.M * a.M;
+    const __amdgpu_buffer_rsrc_t sr = make_rsrc(a.scat, SCAT ? (int64_t)MM * M * 16 : 16);
+    int soff[8];
+    corner_offsets(M, MM, 16, soff);
+    float y[C], R[C];
+    float T = a.exit_T[r];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        y[c] = a.dI[(v * C + c) * HW + pix];
+        R[c] = T * a.background;
+    }
+    float *gp = a.g + a.tile_off[tile] + lane;
+    float *qp = a.q + a.tile_off[tile] + lane;
+    for (int k = K - 1; k >= 0; --k) {
+        float s, len;
+        segment_of(k, K, A.w, a.ds, s, len);
+        const float x = fmaf(s, B.x, A.x), yy = fmaf(s, B.y, A.y), z = fmaf(s, B.z, A.z);
+        int ix, iy, iz;
+        float fx, fy, fz;
+        cell_of(x, a.nx, ix, fx);
+        cell_of(yy, a.ny, iy, fy);
+        cell_of(z, a.nz, iz, fz);
+        float w[8];
+        tri_weights(fx, fy, fz, w);
+        float em[C], sraw;
+        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
+        sample_volume_rsrc<C>(vr, coff, base * elem, w, em, sraw);
+        const float sig = fmaxf(sraw, 0.0f);
+        float S[3] = {0.f, 0.f, 0.f};
+        if constexpr (SCAT) {
+            int jx, jy, jz;
+            float gx, gy, gz;
+            cell_of(x * a.s_scale[0], M, jx, gx);
+            cell_of(yy * a.s_scale[1], M, jy, gy);
+            cell_of(z * a.s_scale[2], M, jz, gz);
+            float ws[8];
+            tri_weights(gx, gy, gz, ws);
+            const int sb = ((int)(__umul24(jz, MM) + __umul24(jy, M)) + jx) * 16;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float4 qv = bload4(sr, sb, soff[c]);
+                S[0] = fmaf(ws[c], qv.x, S[0]);
+                S[1] = fmaf(ws[c], qv.y, S[1]);
+                S[2] = fmaf(ws[c], qv.z, S[2]);
+            }
+            const float as = a.albedo * sig;
+#pragma unroll
+            for (int c = 0; c < C; ++c) em[c] = fmaf(as, S[c], em[c]);
+        }
+        const float xo = sig * len;
+        float e;
+        const float ph = phi_exp(xo, e);
+        const float dph = dphi_f(xo, e);
+        T = T * __expf(xo);  // transmittance in front of sample k
+        const float gk = T * len * ph;
+        float qk = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float dc = T * len * fmaf(a.albedo * S[c], ph, em[c] * len * dph);
+            qk = fmaf(y[c], fmaf(-len, R[c], dc), qk);
+            R[c] = fmaf(gk, em[c], R[c]);
+        }
+        gp[k * kTileRays] = gk;
+        qp[k * kTileRays] = sraw >= 0.0f ? qk : 0.0f;
     }
 }
 
@@ -581,6 +710,7 @@ struct GatherArgs {
     const float4 *rayA, *rayB;
     const uint64_t *tile_off;
     const float *g;
+    const float *q;        // second per-sample buffer (gradient mode)
     const float *y;        // [V][C][H][W]
     const ViewProj *proj;
     float *part;           // [8][acc][cells]
@@ -597,7 +727,8 @@ constexpr float kPixPad = 2e-3f;   // pixels: projection rounding allowance
 
 template <int C, int MODE>
 struct GatherAcc {
-    static constexpr int N = MODE == kGatherCols ? 1 : (MODE == kGatherAdjointCols ? C + 1 : C);
+    static constexpr int N =
+        MODE == kGatherCols ? 1 : ((MODE == kGatherAdjointCols || MODE == kGatherGrad) ? C + 1 : C);
 };
 
 // Each work-item owns one cell (voxel) c and gathers every sample that the
@@ -723,6 +854,17 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                         if constexpr (MODE == kGatherCols) {
 #pragma unroll
                             for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gk, w[c], acc[c][0]);
+                        } else if constexpr (MODE == kGatherGrad) {
+                            const float qk = a.q[(gp - a.g) + k * kTileRays];
+                            float gy[C];
+#pragma unroll
+                            for (int qq = 0; qq < C; ++qq) gy[qq] = gk * yv[qq];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) {
+#pragma unroll
+                                for (int qq = 0; qq < C; ++qq) acc[c][qq] = fmaf(gy[qq], w[c], acc[c][qq]);
+                                acc[c][C] = fmaf(qk, w[c], acc[c][C]);
+                            }
                         } else {
                             float gy[C];
 #pragma unroll
@@ -754,7 +896,8 @@ struct UpdateArgs {
     const float *part;
     float *vol;          // packed volume (updates)
     float *cols;         // column sums (read, or written in kUpdCols)
-    float *out;          // delta [C][N] (kUpdDelta)
+    float *out;          // delta [C][N] (kUpdDelta, kUpdGrad)
+    float *out2;         // extinction gradient [N] (kUpdGrad)
     float *temperature;  // kUpdTemp output
     const float *lut;    // [3][lut_cap]
     int lut_cap, lut_size, fit_channel;
@@ -789,7 +932,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= a.n) return;
     const int jx = (int)(j % a.nx), jy = (int)((j / a.nx) % a.ny), jz = (int)(j / ((int64_t)a.nx * a.ny));
-    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : C);
+    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : (MODE == kUpdGrad ? C + 1 : C));
     float sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0f;
@@ -805,6 +948,10 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
     if constexpr (MODE == kUpdDelta) {
 #pragma unroll
         for (int q = 0; q < C; ++q) a.out[q * a.n + j] = sum[q];
+    } else if constexpr (MODE == kUpdGrad) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) a.out[q * a.n + j] = sum[q];
+        a.out2[j] = sum[C];
     } else if constexpr (MODE == kUpdCols) {
         a.cols[j] = sum[0];
     } else if constexpr (MODE == kUpdTemp) {
@@ -998,9 +1145,10 @@ static hipError_t render_dispatch(const RenderArgs &a, bool emis, bool scat, boo
 
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s)
+                         int frame_channel0, float *out, hipStream_t s, float *exit_T)
 {
     RenderArgs a{};
+    a.exit_T = exit_T;
     a.fC = frame_channels;
     a.fc0 = frame_channel0;
     a.rayA = p->d_rayA;
@@ -1065,6 +1213,45 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
+                                hipStream_t s)
+{
+    GradArgs a{};
+    a.rayA = p->d_rayA;
+    a.rayB = p->d_rayB;
+    a.tile_off = p->d_tile_off;
+    a.tile_order = p->d_tile_order;
+    a.n_launch = p->n_active_tiles;
+    a.vol = p->d_vol;
+    a.scat = p->d_scat;
+    a.exit_T = exit_T;
+    a.dI = dI;
+    a.g = p->d_g;
+    a.q = p->d_q;
+    a.W = p->W;
+    a.H = p->H;
+    a.tiles_x = p->tiles_x;
+    a.tiles_per_view = p->tiles_per_view;
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.M = p->params.scatter_res;
+    a.ds = (float)p->ds;
+    a.albedo = p->params.albedo;
+    a.background = p->params.background;
+    const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    for (int i = 0; i < 3; ++i)
+        a.s_scale[i] = a.M >= 2 ? (float)((double)(a.M - 1) / (double)(n[i] - 1)) : 0.0f;
+    const int nb = (a.n_launch + 3) / 4;
+    if (nb == 0) return hipSuccess;
+    const int C = p->params.channels;
+    if (C == 3 && use_scatter) hipLaunchKernelGGL((adjoint_march_kernel<3, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else if (C == 3) hipLaunchKernelGGL((adjoint_march_kernel<3, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    else if (use_scatter) hipLaunchKernelGGL((adjoint_march_kernel<1, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((adjoint_march_kernel<1, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int C, int MODE>
 static void gather_launch(const GatherArgs &a, hipStream_t s)
 {
@@ -1079,6 +1266,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
     a.rayB = p->d_rayB;
     a.tile_off = p->d_tile_off;
     a.g = p->d_g;
+    a.q = p->d_q;
     a.y = y;
     a.proj = p->d_proj;
     a.part = p->d_part;
@@ -1106,6 +1294,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         case kGatherAdjointCols: gather_launch<3, kGatherAdjointCols>(a, s); break;
         case kGatherCols: gather_launch<3, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<3, kGatherPaper>(a, s); break;
+        case kGatherGrad: gather_launch<3, kGatherGrad>(a, s); break;
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -1114,6 +1303,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         case kGatherAdjointCols: gather_launch<1, kGatherAdjointCols>(a, s); break;
         case kGatherCols: gather_launch<1, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<1, kGatherPaper>(a, s); break;
+        case kGatherGrad: gather_launch<1, kGatherGrad>(a, s); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -1128,9 +1318,10 @@ static void update_launch(const UpdateArgs &a, hipStream_t s)
 
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s)
+                         int fit_channel, hipStream_t s, float *out2)
 {
     UpdateArgs a{};
+    a.out2 = out2;
     a.part = p->d_part;
     a.vol = p->d_vol;
     a.cols = p->d_cols;
@@ -1163,6 +1354,7 @@ hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, flo
         RTE_UPD(kUpdSart)
         RTE_UPD(kUpdMlem)
         RTE_UPD(kUpdPaper)
+        RTE_UPD(kUpdGrad)
     case kUpdTemp: update_launch<1, kUpdTemp>(a, s); break;
     default: return hipErrorInvalidValue;
     }

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
 
 RTE_OK, RTE_ERR_INVALID_ARG, RTE_ERR_BUDGET, RTE_ERR_HIP, RTE_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 KERNELS = {"rays": 0, "render": 1, "inscatter": 2, "gather": 3, "update": 4, "temp_map": 5,
-           "pack": 6, "weights": 7, "colsum": 8}
+           "pack": 6, "weights": 7, "colsum": 8, "adjoint": 9}
+RTE_PLAN_GRADIENTS = 1
 UPDATES = {"sart": 0, "paper": 1, "mlem": 2}
 BP_MODES = {"adjoint": 0, "paper": 1}
 
@@ -47,7 +48,7 @@ class Grid(ct.Structure):
 class RenderParams(ct.Structure):
     _fields_ = [("channels", ct.c_int32), ("step_vox", ct.c_float), ("albedo", ct.c_float),
                 ("background", ct.c_float), ("scatter_res", ct.c_int32),
-                ("scatter_dirs", ct.c_int32), ("scatter_step", ct.c_float)]
+                ("scatter_dirs", ct.c_int32), ("scatter_step", ct.c_float), ("flags", ct.c_int32)]
 
 
 class ReconParams(ct.Structure):
@@ -106,6 +107,8 @@ def lib():
     L.rte_plan_counts.argtypes = [vp, P(ct.c_uint64), P(ct.c_uint64)]
     L.rte_ray_table.argtypes = [vp, vp, vp, vp, vp]
     L.rte_render.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.rte_render_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.rte_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.rte_inscatter.argtypes = [vp, vp, vp, vp, vp]
     L.rte_backproject.argtypes = [vp, vp, vp, vp, i32, P(ReconParams), vp]
     L.rte_reconstruct.argtypes = [vp, vp, vp, vp, i32, P(ReconParams), vp]
@@ -145,10 +148,12 @@ def _cams(rig):
     return arr, V
 
 
-def _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step):
+def _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step,
+            flags=0):
     p = RenderParams()
     p.channels, p.step_vox, p.albedo, p.background = int(channels), step_vox, albedo, background
     p.scatter_res, p.scatter_dirs, p.scatter_step = int(scatter_res), int(scatter_dirs), scatter_step
+    p.flags = int(flags)
     return p
 
 
@@ -174,9 +179,10 @@ def _ptr(t, shape=None, name="tensor"):
 
 
 def workspace_bytes(grid, rig, channels=1, step_vox=0.5, albedo=0.0, background=0.0, scatter_res=0,
-                    scatter_dirs=32, scatter_step=0.5):
+                    scatter_dirs=32, scatter_step=0.5, gradients=False):
     cams, V = _cams(rig)
-    p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step)
+    p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step,
+                RTE_PLAN_GRADIENTS if gradients else 0)
     return int(lib().rte_plan_workspace_bytes(ct.byref(_grid(grid)), cams, V, ct.byref(p)))
 
 
@@ -184,7 +190,8 @@ class Plan:
     """A grid + camera rig + forward-model setup with its device workspaces."""
 
     def __init__(self, grid, rig, channels=1, step_vox=0.5, albedo=0.0, background=0.0,
-                 scatter_res=0, scatter_dirs=32, scatter_step=0.5, hbm_budget_bytes=0):
+                 scatter_res=0, scatter_dirs=32, scatter_step=0.5, hbm_budget_bytes=0,
+                 gradients=False):
         import torch
         self._h = None
         self.grid = grid
@@ -192,8 +199,9 @@ class Plan:
         self.V, self.H, self.W = int(len(rig.fx)), int(rig.height), int(rig.width)
         self.scatter_res = int(scatter_res)
         cams, V = _cams(rig)
+        self.gradients = bool(gradients)
         self._p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs,
-                          scatter_step)
+                          scatter_step, RTE_PLAN_GRADIENTS if gradients else 0)
         h = ct.c_void_p()
         torch.cuda.init()
         _check(lib().rte_plan_create(ct.byref(h), ct.byref(_grid(grid)), cams, V,
@@ -234,6 +242,29 @@ class Plan:
                                 _ptr(inscatter, (C, M, M, M), "inscatter"),
                                 _ptr(out, self.img_shape(), "images"), _stream()))
         return out
+
+    def render_forward(self, emission, extinction, inscatter=None):
+        """Images and the exit transmittance of every ray (for render_backward)."""
+        C, M = self.channels, self.scatter_res
+        out = self._new(self.img_shape())
+        exit_T = self._new((self.V, self.H, self.W))
+        _check(lib().rte_render_forward(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
+                                        _ptr(extinction, self.vol_shape, "extinction"),
+                                        _ptr(inscatter, (C, M, M, M), "inscatter"),
+                                        _ptr(out), _ptr(exit_T), _stream()))
+        return out, exit_T
+
+    def render_backward(self, emission, extinction, inscatter, exit_T, grad_images):
+        """(dL/d emission, dL/d extinction) given dL/d images."""
+        C, M = self.channels, self.scatter_res
+        g_em = self._new((C,) + self.vol_shape)
+        g_sig = self._new(self.vol_shape)
+        _check(lib().rte_render_backward(
+            self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
+            _ptr(extinction, self.vol_shape, "extinction"), _ptr(inscatter, (C, M, M, M), "inscatter"),
+            _ptr(exit_T, (self.V, self.H, self.W), "exit_T"),
+            _ptr(grad_images, self.img_shape(), "grad_images"), _ptr(g_em), _ptr(g_sig), _stream()))
+        return g_em, g_sig
 
     def inscatter(self, emission, extinction, out=None):
         C, M = self.channels, self.scatter_res

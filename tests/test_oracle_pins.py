@@ -450,3 +450,45 @@ def test_em_step_matches_dense_formula_and_likelihood_ascends():
         cur = ll(x)
         assert cur >= prev - 1e-12 * abs(prev)
         prev = cur
+
+
+# ---------------------------------------------------- gradient of the render
+def test_render_gradient_matches_finite_differences():
+    """dL/d(eps, sigma) through the nonlinear render (with in-scattering held
+    fixed and a background) equals central differences of the oracle's own
+    render: an independent route through orc_render only."""
+    g = synth.Grid(7, 6, 5)
+    rig = synth.ring_rig(3, 10, 9, radius=2.2, elevation_jitter_deg=15, seed=3)
+    rng = np.random.default_rng(0)
+    em = rng.uniform(0.2, 1.0, size=(2,) + g.shape_zyx)
+    sig = rng.uniform(0.5, 3.0, size=g.shape_zyx)
+    S = rng.uniform(0.1, 0.5, size=(2, 4, 4, 4))
+    F = rng.uniform(0.0, 0.3, size=(3, 2, 9, 10))
+    kw = dict(albedo=0.3, background=0.1, inscatter=S)
+    loss = lambda e, s: 0.5 * ((oracle.render(g, rig, e, s, **kw) - F) ** 2).sum()
+    I = oracle.render(g, rig, em, sig, **kw)
+    de, dsg = oracle.render_grad(g, rig, em, sig, I - F, **kw)
+    h = 1e-6
+    for idx in [(0, 2, 3, 3), (1, 1, 2, 4), (0, 3, 1, 2), (1, 4, 5, 6)]:
+        e1, e2 = em.copy(), em.copy()
+        e1[idx] += h
+        e2[idx] -= h
+        fd = (loss(e1, sig) - loss(e2, sig)) / (2 * h)
+        assert abs(fd - de[idx]) <= 1e-6 * max(abs(fd), 1e-3)
+    for idx in [(2, 3, 3), (1, 2, 4), (3, 1, 2), (0, 0, 0), (4, 5, 6)]:
+        s1, s2 = sig.copy(), sig.copy()
+        s1[idx] += h
+        s2[idx] -= h
+        fd = (loss(em, s1) - loss(em, s2)) / (2 * h)
+        assert abs(fd - dsg[idx]) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_emission_gradient_is_the_adjoint():
+    """Without scattering or background, dL/d eps = A^T (I - F)."""
+    g = synth.Grid(6, 6, 6)
+    rig = synth.ring_rig(2, 8, 8, seed=1, elevation_jitter_deg=5)
+    rng = np.random.default_rng(1)
+    em, sig = rng.uniform(size=(1,) + g.shape_zyx), rng.uniform(0.1, 2, size=g.shape_zyx)
+    y = rng.normal(size=(2, 1, 8, 8))
+    de, _ = oracle.render_grad(g, rig, em, sig, y)
+    np.testing.assert_allclose(de, oracle.backproject_adjoint(g, rig, sig, y), rtol=1e-12, atol=1e-15)
