@@ -80,13 +80,29 @@ def test_autograd_function_matches_backward_and_finite_differences():
                 assert abs(a - g) <= 2e-2 * max(abs(g), 1e-4), (idx, a, g)
 
 
-def test_full_size_gradient_against_finite_differences():
-    """The differentiation workload: 256^3 RGB emission + extinction with single
-    scattering, 12 views of 1024x768; L2 image loss; central differences with
-    h = 1e-3 on 64 random voxels inside the flame."""
-    import torch
+def _full_size_case(views):
     g, em_gt, sig_gt = synth.colour_volume(seed=4, n=256)
     rig = synth.ring_rig(12, 1024, 768)
+    if views < 12:
+        rig = rig.subset(range(views))
+    return g, f32(em_gt), f32(sig_gt), rig
+
+
+def test_full_size_gradient_against_finite_differences():
+    """The differentiation workload: 256^3 RGB emission + extinction with single
+    scattering, 12 views of 1024x768, L2 image loss. Central differences with
+    h = 1e-3 on 64 random voxels inside the flame (32 emission, 32 extinction).
+
+    Emission differences only change the perturbed samples, so they are
+    checked entry by entry. An extinction perturbation changes the
+    transmittance of everything behind it: the FP32 rounding of the two full
+    renders then enters the difference at about 1% of it per entry (the
+    per-pixel change is ~1e-5 of the pixel value), so at h = 1e-3 the 32
+    entries are checked jointly (least-squares slope and correlation), and
+    entry by entry at h = 1e-2 where that noise is ten times smaller and the
+    truncation error is still ~(h/sigma)^2."""
+    import torch
+    g, em_gt, sig_gt, rig = _full_size_case(12)
     say("full-size gradient FD")
     with rte().Plan(g, rig, channels=3, step_vox=STEP, albedo=0.3, scatter_res=32, scatter_dirs=32,
                     gradients=True) as p:
@@ -100,28 +116,61 @@ def test_full_size_gradient_against_finite_differences():
 
         def L(e, s):
             return 0.5 * ((p.render(e, s, S) - F).double() ** 2).sum().item()
+
+        def fd(base, idx, h, emission):
+            plus, minus = base.clone(), base.clone()
+            plus[idx] += h
+            minus[idx] -= h
+            dx = (plus[idx] - minus[idx]).item()
+            if emission:
+                return (L(plus, sig) - L(minus, sig)) / dx
+            return (L(em, plus) - L(em, minus)) / dx
+
         rng = np.random.default_rng(11)
         inside = np.argwhere(sig_gt > 0.5)
         picks = inside[rng.choice(len(inside), size=64, replace=False)]
-        errs = []
+        e_err, s_fd, s_an, s_err = [], [], [], []
         for i, (z, yy, x) in enumerate(picks):
-            if i % 2 == 0:
-                ch = int(rng.integers(0, 3))
-                base, idx, grad = em, (ch, z, yy, x), de
+            if i < 32:
+                idx = (int(rng.integers(0, 3)), z, yy, x)
+                gv = de[idx].item()
+                e_err.append(abs(fd(em, idx, 1e-3, True) - gv) / max(abs(gv), 1e-3 * float(de.abs().max())))
             else:
-                base, idx, grad = sig, (z, yy, x), ds
-            plus, minus = base.clone(), base.clone()
-            plus[idx] += 1e-3
-            minus[idx] -= 1e-3
-            dx = (plus[idx] - minus[idx]).item()
-            if base is em:
-                fd = (L(plus, sig) - L(minus, sig)) / dx
-            else:
-                fd = (L(em, plus) - L(em, minus)) / dx
-            gval = grad[idx].item()
-            errs.append(abs(fd - gval) / max(abs(gval), 1e-3 * float(grad.abs().max())))
-    errs = np.array(errs)
-    assert np.median(errs) <= 5e-3 and errs.max() <= 3e-2, errs
+                idx = (z, yy, x)
+                gv = ds[idx].item()
+                s_fd.append(fd(sig, idx, 1e-3, False))
+                s_an.append(gv)
+                s_err.append(abs(fd(sig, idx, 1e-2, False) - gv) / max(abs(gv), 1e-3 * float(ds.abs().max())))
+    e_err, s_err = np.array(e_err), np.array(s_err)
+    s_fd, s_an = np.array(s_fd), np.array(s_an)
+    slope = float((s_fd * s_an).sum() / (s_an * s_an).sum())
+    r = float(np.corrcoef(s_fd, s_an)[0, 1])
+    assert e_err.max() <= 1e-2, e_err
+    assert abs(slope - 1.0) <= 1e-2 and r >= 0.999, (slope, r)
+    assert np.median(s_err) <= 5e-3 and s_err.max() <= 3e-2, s_err
+
+
+def test_full_size_gradient_matches_oracle_on_two_views():
+    """GPU gradient against the FP64 oracle gradient at the full grid (256^3,
+    RGB + extinction, single scattering) and image size (1024x768), on two of
+    the twelve views so that the oracle finishes in seconds."""
+    g, em_gt, sig_gt, rig = _full_size_case(2)
+    say("full-size gradient vs oracle, 2 views")
+    with rte().Plan(g, rig, channels=3, step_vox=STEP, albedo=0.3, scatter_res=32, scatter_dirs=32,
+                    gradients=True) as p:
+        emg, sgg = dev(em_gt), dev(sig_gt)
+        S = p.inscatter(emg, sgg)
+        F = p.render(emg, sgg, S)
+        em = f32(em_gt * 0.8)
+        sig = f32(sig_gt * 0.9 + 0.02)
+        img, exit_T = p.render_forward(dev(em), dev(sig), S)
+        y = host((img - F).contiguous())
+        de, ds = p.render_backward(dev(em), dev(sig), S, exit_T, dev(y))
+        de, ds, S = host(de), host(ds), host(S)
+    de_o, ds_o = oracle.render_grad(g, rig, as64(em), as64(sig), y, step_vox=STEP, albedo=0.3,
+                                    inscatter=S)
+    assert rel_max(de, de_o) <= 2e-4
+    assert rel_max(ds, ds_o) <= 2e-4
 
 
 def test_adam_reconstruction_reduces_loss():
