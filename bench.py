@@ -39,6 +39,9 @@ WORKLOADS = {
     "colour": dict(n=128, views=8, W=512, H=512, C=3, albedo=0.3, M=32, dirs=32, iters=20),
     "temperature": dict(n=128, views=8, W=512, H=512, C=1, albedo=0.0, M=0, dirs=32, iters=30),
     "tiny": dict(n=32, views=4, W=64, H=64, C=1, albedo=0.0, M=0, dirs=32, iters=5),
+    # gradient-based reconstruction: one step = forward march + adjoint march +
+    # gradient gather + Adam update of (emission, extinction)
+    "diff": dict(n=256, views=12, W=1024, H=768, C=3, albedo=0.3, M=32, dirs=32, iters=50),
 }
 
 
@@ -125,7 +128,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     wl = WORKLOADS[args.workload]
     print(f"[bench] workload {args.workload}: building inputs", file=sys.stderr, flush=True)
-    if args.workload == "colour":
+    if args.workload in ("colour", "diff"):
         g, em, sig = synth.colour_volume(args.seed, n=wl["n"])
     elif args.workload == "tiny":
         g, em, sig = synth.tiny_volume(args.seed, n=wl["n"])
@@ -134,7 +137,7 @@ def main():
     rig = synth.ring_rig(wl["views"], wl["W"], wl["H"])
     C = wl["C"]
     plan = rte.Plan(g, rig, channels=C, step_vox=0.5, albedo=wl["albedo"],
-                    scatter_res=wl["M"], scatter_dirs=wl["dirs"])
+                    scatter_res=wl["M"], scatter_dirs=wl["dirs"], gradients=args.workload == "diff")
     dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
     if args.workload == "temperature":
         tp = rte.TempParams()
@@ -144,6 +147,25 @@ def main():
         frames[:, 1] = plan.render(em3[1:2].contiguous(), sg)[:, 0]
         x0 = torch.full_like(Td, 800.0)
         step_fn = lambda x, k: plan.reconstruct_temperature(frames, x, k, tp)
+    elif args.workload == "diff":
+        from paper_1809_06417_amd import autograd
+        emd, sigd = dev(em), dev(sig)
+        S = plan.inscatter(emd, sigd)
+        frames = plan.render(emd, sigd, S)
+        x0 = (torch.full_like(emd, 0.1), torch.full_like(sigd, 0.5))
+
+        def step_fn(x, k):
+            em_p, sg_p = x[0].requires_grad_(True), x[1].requires_grad_(True)
+            opt = torch.optim.Adam([em_p, sg_p], lr=0.02)
+            for _ in range(k):
+                opt.zero_grad(set_to_none=False)
+                loss = 0.5 * ((autograd.render(plan, em_p, sg_p, S) - frames) ** 2).sum()
+                loss.backward()
+                opt.step()
+                with torch.no_grad():
+                    em_p.clamp_(min=0.0)
+                    sg_p.clamp_(min=0.0)
+            return em_p
     else:
         emd, sigd = dev(em), dev(sig)
         S = plan.inscatter(emd, sigd) if wl["albedo"] > 0 else None
@@ -154,13 +176,14 @@ def main():
     print(f"[bench] plan: {plan.samples} samples/iteration, {plan.hit_rays} hit rays, "
           f"{plan.device_bytes / 2**20:.0f} MiB workspace", file=sys.stderr, flush=True)
 
-    x = x0.clone()
+    fresh = (lambda: tuple(t.clone() for t in x0)) if isinstance(x0, tuple) else (lambda: x0.clone())
+    x = fresh()
     if args.warmup > 0:
         step_fn(x, args.warmup)
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    x = x0.clone()
+    x = fresh()
     plan.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -175,6 +198,10 @@ def main():
     value = samples * args.steps / elapsed
     b_render, b_gather = bytes_per_sample(C, wl["albedo"] > 0)
     cands = {"render": b_render, "gather": b_gather}
+    if args.workload == "diff":
+        # the adjoint march re-reads what the render reads; the gradient gather
+        # accumulates C emission + 1 extinction values per corner
+        cands = {"render": b_render, "adjoint": b_render, "gather": 8 * (C + 1) * 4}
     per_kernel = {}
     for k, (ms, n) in ktimes.items():
         if n:
@@ -190,7 +217,7 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
-        if args.workload == "temperature":
+        if args.workload in ("temperature", "diff"):
             base = None
         else:
             base = cpu_baseline(g, rig, em, sig, frames.cpu().numpy(), wl,

@@ -167,7 +167,7 @@ std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, co
 }
 
 struct Sizes {
-    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, dirs, y, part, cols, lut, total;
+    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, y, part, cols, lut, total;
     int part_acc, lut_cap;
 };
 
@@ -189,12 +189,13 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
     s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
     s.dirs = sizeof(float4) * kMaxDirs;
+    s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * C * M * M * M : sizeof(float);
     s.y = sizeof(float) * (size_t)d.n_rays * C;
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
-    s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.dirs + s.y +
-              s.part + s.cols + s.lut;
+    s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.scat_part + s.dirs +
+              s.y + s.part + s.cols + s.lut;
     return s;
 }
 
@@ -284,7 +285,7 @@ void free_plan(rte_plan *p)
     }
     for (auto e : p->event_pool) hipEventDestroy(e);
     void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
-                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_dirs, p->d_y, p->d_part,
+                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_scat_part, p->d_dirs, p->d_y, p->d_part,
                     p->d_cols, p->d_lut};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -461,7 +462,8 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     p->lut_cap = full.lut_cap;
     if ((rc = dev_alloc(&p->d_g, full.g, acc)) || (full.q && (rc = dev_alloc(&p->d_q, full.q, acc))) ||
         (rc = dev_alloc(&p->d_vol, full.vol, acc)) ||
-        (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
+        (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_scat_part, full.scat_part, acc)) ||
+        (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
         (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
         (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)))
         return bail(rc);

@@ -4,8 +4,10 @@
 // K1 render      : one work-item per pixel ray, one wave per 8x8 pixel tile,
 //                  front-to-back march (Eq. 5-8) with fused residual epilogue
 //                  and optional per-sample weight output.
-// K2 in-scatter  : 32 lanes per in-scatter node, one direction per lane,
-//                  fixed-order butterfly sum (Eq. 5 third term, Eq. 9, g = 0).
+// K2 in-scatter  : direction-major march from every in-scatter node (a wave
+//                  per 4x4x4 node brick, directions spread over the XCDs),
+//                  then a fixed-order sum over directions (Eq. 5 third
+//                  term, Eq. 9 at g = 0).
 // K3 gather      : atomics-free back-projection (Alg. 2 adjustment): each
 //                  work-item owns one voxel (cell) and gathers, per view, the
 //                  samples of the rays through that cell into per-corner
@@ -608,86 +610,98 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
 struct ScatArgs {
     const float *vol;
     const float4 *dirs;  // unit directions in voxel units per world unit (xyz)
+    float *dpart;        // per-direction sums [ndirs][C][M^3]
     float4 *scat;        // packed output (rgb, 0)
     float *planar;       // optional [C][M^3]
     int nx, ny, nz, M, ndirs;
+    int nbricks, blocks_per_dir, dirs_per_xcd;
     float p_scale[3];    // in-scatter node index -> fine grid coords
     float ds;            // world step
     float inv_ndirs;
 };
 
-// A block owns a 4x4x4 brick of in-scatter nodes and kScatGroups waves; wave
-// w marches directions w, w + kScatGroups, ... from all 64 nodes of the brick,
-// so the 64 rays of a wave are parallel and neighbouring (coherent gathers).
-// The per-wave partial sums are added in wave order through LDS.
-#ifndef RTE_SCAT_GROUPS
-#define RTE_SCAT_GROUPS 8
-#endif
-constexpr int kScatGroups = RTE_SCAT_GROUPS;
-
+// Direction-major march: XCD x (blocks b with b % 8 == x) takes directions
+// x, x + 8, x + 16, ... in turn and marches each one from every node of the
+// in-scatter grid before moving on (a wave = one 4x4x4 brick of nodes, a
+// block = four bricks). The waves resident on one XCD therefore sweep the
+// volume along parallel, neighbouring rays and share that XCD's L2. Each
+// (direction, node) sum is stored; the directions are added in order by
+// inscatter_reduce_kernel.
 template <int C>
-__global__ __launch_bounds__(64 * kScatGroups) void inscatter_kernel(ScatArgs a)
+__global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
 {
-    __shared__ float red[kScatGroups][64][C];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int d = x + 8 * (j / a.blocks_per_dir);
+    const int brick = (j % a.blocks_per_dir) * 4 + w;
+    if (d >= a.ndirs || brick >= a.nbricks) return;
     const int M = a.M, bm = (M + 3) >> 2;
-    const int b = blockIdx.x;
-    const int bx = b % bm, by = (b / bm) % bm, bz = b / (bm * bm);
+    const int bx = brick % bm, by = (brick / bm) % bm, bz = brick / (bm * bm);
     const int mx = bx * 4 + (l & 3), my = by * 4 + ((l >> 2) & 3), mz = bz * 4 + (l >> 4);
-    const bool valid = mx < M && my < M && mz < M;
+    if (mx >= M || my >= M || mz >= M) return;
     const float px = (float)mx * a.p_scale[0], py = (float)my * a.p_scale[1],
                 pz = (float)mz * a.p_scale[2];
     const float tx = (float)(a.nx - 1), ty = (float)(a.ny - 1), tz = (float)(a.nz - 1);
-    const auto *vol = reinterpret_cast<const typename Packed<C>::T *>(a.vol);
-    const int nxy = a.nx * a.ny;
+    const int nx = a.nx, nxy = a.nx * a.ny;
+    constexpr int elem = C == 3 ? 16 : 8;
+    const __amdgpu_buffer_rsrc_t vr = make_rsrc(a.vol, (int64_t)nxy * a.nz * elem);
+    int coff[8];
+    corner_offsets(nx, nxy, elem, coff);
+    const float4 u = a.dirs[d];
+    // exit distance from an interior point (world units)
+    float ell = INFINITY;
+    if (u.x > 0.f) ell = fminf(ell, (tx - px) / u.x);
+    if (u.x < 0.f) ell = fminf(ell, -px / u.x);
+    if (u.y > 0.f) ell = fminf(ell, (ty - py) / u.y);
+    if (u.y < 0.f) ell = fminf(ell, -py / u.y);
+    if (u.z > 0.f) ell = fminf(ell, (tz - pz) / u.z);
+    if (u.z < 0.f) ell = fminf(ell, -pz / u.z);
+    ell = fmaxf(ell, 0.0f);
+    const int K = ell > 0.0f ? (int)ceilf(ell / a.ds) : 0;
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    for (int d = w; valid && d < a.ndirs; d += kScatGroups) {
-        const float4 u = a.dirs[d];
-        // exit distance from an interior point (world units)
-        float ell = INFINITY;
-        if (u.x > 0.f) ell = fminf(ell, (tx - px) / u.x);
-        if (u.x < 0.f) ell = fminf(ell, -px / u.x);
-        if (u.y > 0.f) ell = fminf(ell, (ty - py) / u.y);
-        if (u.y < 0.f) ell = fminf(ell, -py / u.y);
-        if (u.z > 0.f) ell = fminf(ell, (tz - pz) / u.z);
-        if (u.z < 0.f) ell = fminf(ell, -pz / u.z);
-        ell = fmaxf(ell, 0.0f);
-        const int K = ell > 0.0f ? (int)ceilf(ell / a.ds) : 0;
-        float T = 1.0f;
-        for (int k = 0; k < K; ++k) {
-            float s, len;
-            segment_of(k, K, ell, a.ds, s, len);
-            int ix, iy, iz;
-            float fx, fy, fz;
-            cell_of(fmaf(s, u.x, px), a.nx, ix, fx);
-            cell_of(fmaf(s, u.y, py), a.ny, iy, fy);
-            cell_of(fmaf(s, u.z, pz), a.nz, iz, fz);
-            float wt[8];
-            tri_weights(fx, fy, fz, wt);
-            float em[C], sig;
-            sample_volume<C>(vol, a.nx, nxy, ix, iy, iz, wt, em, sig);
-            sig = fmaxf(sig, 0.0f);
-            float e;
-            const float wg = T * len * phi_exp(sig * len, e);
+    float T = 1.0f;
+    for (int k = 0; k < K; ++k) {
+        float s, len;
+        segment_of(k, K, ell, a.ds, s, len);
+        int ix, iy, iz;
+        float fx, fy, fz;
+        cell_of(fmaf(s, u.x, px), a.nx, ix, fx);
+        cell_of(fmaf(s, u.y, py), a.ny, iy, fy);
+        cell_of(fmaf(s, u.z, pz), a.nz, iz, fz);
+        float wt[8];
+        tri_weights(fx, fy, fz, wt);
+        float em[C], sig;
+        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
+        sample_volume_rsrc<C>(vr, coff, base * elem, wt, em, sig);
+        sig = fmaxf(sig, 0.0f);
+        float e;
+        const float wg = T * len * phi_exp(sig * len, e);
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = fmaf(wg, em[c], acc[c]);
-            T *= e;
-        }
+        for (int c = 0; c < C; ++c) acc[c] = fmaf(wg, em[c], acc[c]);
+        T *= e;
     }
+    const int m3 = M * M * M;
+    const int m = (mz * M + my) * M + mx;
 #pragma unroll
-    for (int c = 0; c < C; ++c) red[w][l][c] = acc[c];
-    __syncthreads();
-    if (w != 0 || !valid) return;
+    for (int c = 0; c < C; ++c) a.dpart[(int64_t)(d * C + c) * m3 + m] = acc[c];
+}
+
+// S_c(node) = (1 / ndirs) sum_d, the directions added in index order.
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_reduce_kernel(ScatArgs a)
+{
+    const int m3 = a.M * a.M * a.M;
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= m3) return;
     float tot[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         tot[c] = 0.0f;
-        for (int g = 0; g < kScatGroups; ++g) tot[c] += red[g][l][c];
+        for (int d = 0; d < a.ndirs; ++d) tot[c] += a.dpart[(int64_t)(d * C + c) * m3 + m];
         tot[c] *= a.inv_ndirs;
     }
-    const int m = (mz * M + my) * M + mx;
     float4 o = make_float4(tot[0], 0.f, 0.f, 0.f);
     if constexpr (C == 3) {
         o.y = tot[1];
@@ -695,7 +709,6 @@ __global__ __launch_bounds__(64 * kScatGroups) void inscatter_kernel(ScatArgs a)
     }
     a.scat[m] = o;
     if (a.planar) {
-        const int m3 = M * M * M;
         a.planar[m] = o.x;
         if constexpr (C == 3) {
             a.planar[m3 + m] = o.y;
@@ -1188,6 +1201,7 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     ScatArgs a{};
     a.vol = p->d_vol;
     a.dirs = p->d_dirs;
+    a.dpart = p->d_scat_part;
     a.scat = p->d_scat;
     a.planar = planar_out;
     a.nx = p->grid.nx;
@@ -1205,11 +1219,18 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     a.ds = (float)(p->params.scatter_step * hs_min);
     a.inv_ndirs = 1.0f / (float)a.ndirs;
     const int bm = (a.M + 3) / 4;
-    const int nb = bm * bm * bm;
-    if (p->params.channels == 3)
-        hipLaunchKernelGGL(inscatter_kernel<3>, dim3(nb), dim3(64 * kScatGroups), 0, s, a);
-    else
-        hipLaunchKernelGGL(inscatter_kernel<1>, dim3(nb), dim3(64 * kScatGroups), 0, s, a);
+    a.nbricks = bm * bm * bm;
+    a.blocks_per_dir = (a.nbricks + 3) / 4;
+    a.dirs_per_xcd = (a.ndirs + 7) / 8;
+    const int nb = 8 * a.dirs_per_xcd * a.blocks_per_dir;
+    const int64_t m3 = (int64_t)a.M * a.M * a.M;
+    if (p->params.channels == 3) {
+        hipLaunchKernelGGL(inscatter_march_kernel<3>, dim3(nb), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(inscatter_reduce_kernel<3>, dim3(blocks_for(m3)), dim3(kBlock), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(inscatter_march_kernel<1>, dim3(nb), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(inscatter_reduce_kernel<1>, dim3(blocks_for(m3)), dim3(kBlock), 0, s, a);
+    }
     return hipGetLastError();
 }
 
