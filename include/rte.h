@@ -101,14 +101,35 @@ typedef enum {
 /* Reconstruction parameters.
  *  update        an rte_update value.
  *  lambda        relaxation (SART, MLEM); 1 is the plain step.
- *  clamp_nonneg  clamp the emission at 0 after each update (SART, PAPER).
+ *  clamp_nonneg  clamp the emission at 0 after each update.
  *  alpha_l, alpha_d, tau   paper-mode constants of Eq. 10 and Eq. 12
- *                (Sec. 5.1 uses 0.001, 1, 0.05; D is measured in voxels). */
+ *                (Sec. 5.1 uses 0.001, 1, 0.05; D is measured in voxels).
+ *  g_sigma, seed paper mode: every sample's adjustment is weighted by a gain
+ *                G(s) = 1 + g_sigma * z (Eq. 11), z standard normal from a
+ *                Philox-4x32-10 counter keyed by seed, counter (k, pixel,
+ *                view, iteration) and Box-Muller; g_sigma = 0 gives G = 1.
+ *  use_mask, flame_threshold   only flame rays -- pixels where some channel
+ *                of the frame exceeds the threshold (Sec. 4.1) -- enter the
+ *                adjustment (and the column sums).
+ *  use_hull, outside_value     reconstruct only key points inside the visual
+ *                hull of the flame rays (Alg. 1); the others are set to
+ *                outside_value and left alone (the paper uses a small
+ *                negative number).
+ *  stop_tol      > 0: stop once the image RMS over the adjusted pixels of two
+ *                successive iterations differs by less (Sec. 3; the paper
+ *                uses 0.01 on its 0-255 scale); iters is then a maximum. */
 typedef struct {
     int32_t update;
     float lambda;
     int32_t clamp_nonneg;
     float alpha_l, alpha_d, tau;
+    float g_sigma;
+    uint64_t seed;
+    int32_t use_mask;
+    float flame_threshold;
+    int32_t use_hull;
+    float outside_value;
+    float stop_tol;
 } rte_recon_params;
 
 /* Colour-temperature mapping (Eq. 13; Sec. 3.3). The LUT holds, at lut_size
@@ -228,6 +249,23 @@ int rte_backproject(rte_plan *plan, const float *extinction, const float *residu
  * (in: start volume, out: result; warm start = pass the previous result). */
 int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction, float *emission,
                     int32_t iters, const rte_recon_params *params, void *stream);
+
+/* Updates made by the last rte_reconstruct on this plan and, when its stop
+ * rule was on, the image RMS of each rendered iteration: n_errors receives
+ * how many were recorded, at most max_errors are copied to errors (either
+ * may be NULL). */
+int rte_reconstruct_stats(const rte_plan *plan, int32_t *iters_done, int32_t *n_errors, float *errors,
+                          int32_t max_errors);
+
+/* Flame-pixel mask (Sec. 4.1): mask [V][H][W] = 1 where some channel of
+ * frames [V][C][H][W] exceeds threshold, else 0 (C = the plan's channels). */
+int rte_flame_mask(rte_plan *plan, const float *frames, float threshold, float *mask, void *stream);
+
+/* Visual hull (Alg. 1): inside [nz][ny][nx] (int32) = 1 for key points that,
+ * for every view, are a corner of a cell holding a sample of a flame ray;
+ * flame rays are the pixels where mask [V][H][W] is non-zero (NULL: every
+ * pixel). At most 64 views. */
+int rte_visual_hull(rte_plan *plan, const float *mask, int32_t *inside, void *stream);
 
 /* Temperature fit (Sec. 3.3): per iteration, map T -> (eps_ch, sigma) through
  * the LUT, render the fitted channel, back-project the frame/render ratio

@@ -14,7 +14,8 @@ import numpy as np
 __all__ = [
     "lib", "ray_table", "render", "inscatter", "backproject_adjoint", "backproject_paper",
     "reconstruct", "planck", "band_radiance", "TempParams", "temp_lut", "temp_map",
-    "temp_invert", "temperature_fit", "num_threads", "render_grad",
+    "temp_invert", "temperature_fit", "num_threads", "render_grad", "philox4x32_10",
+    "sample_gain", "flame_mask", "visual_hull", "reconstruct_ext",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +31,14 @@ class _Camera(ct.Structure):
 
 class _Grid(ct.Structure):
     _fields_ = [("n", ct.c_int32 * 3), ("lo", ct.c_double * 3), ("hi", ct.c_double * 3)]
+
+
+class _ReconParams(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("lam", ct.c_double), ("clamp_nonneg", ct.c_int32),
+                ("alpha_l", ct.c_double), ("alpha_d", ct.c_double), ("tau", ct.c_double),
+                ("g_sigma", ct.c_double), ("seed", ct.c_uint64), ("use_mask", ct.c_int32),
+                ("flame_threshold", ct.c_double), ("use_hull", ct.c_int32),
+                ("outside_value", ct.c_double), ("stop_tol", ct.c_double)]
 
 
 class _TempParams(ct.Structure):
@@ -58,6 +67,16 @@ def lib():
                                          dp, dp, i32, i32, d, i32, d, d, d, dp]
         _lib.orc_render_grad.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, dp, dp, i32, dp,
                                          dp, dp, dp]
+        u32p = P(ct.c_uint32)
+        _lib.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        _lib.orc_philox4x32_10.restype = None
+        _lib.orc_sample_gain.argtypes = [ct.c_uint64, i32, i32, ct.c_int64, i32, d]
+        _lib.orc_sample_gain.restype = d
+        _lib.orc_flame_mask.argtypes = [dp, i32, i32, ct.c_long, d, dp]
+        _lib.orc_flame_mask.restype = None
+        _lib.orc_visual_hull.argtypes = [P(_Grid), P(_Camera), i32, d, dp, P(ct.c_int32)]
+        _lib.orc_reconstruct_ext.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d,
+                                             dp, dp, dp, i32, P(_ReconParams), dp, P(ct.c_int32)]
         _lib.orc_planck.argtypes = [d, d]
         _lib.orc_planck.restype = d
         _lib.orc_band_radiance.argtypes = [d, d, d, i32]
@@ -263,3 +282,58 @@ def temperature_fit(grid, rig, tp: TempParams, lut, frames, T0, iters, *, step_v
                                      _dp(_f64(frames)), _dp(T), int(iters), float(lam), _dp(res)),
            "temperature_fit")
     return (T, res[:iters]) if return_residuals else T
+
+
+def philox4x32_10(ctr, key):
+    c = (ct.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ct.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ct.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def sample_gain(seed, it, view, pixel, k, g_sigma):
+    return float(lib().orc_sample_gain(int(seed), int(it), int(view), int(pixel), int(k),
+                                       float(g_sigma)))
+
+
+def flame_mask(frames, threshold):
+    F = _f64(frames)
+    V, C, H, W = F.shape
+    m = np.zeros((V, H, W))
+    lib().orc_flame_mask(_dp(F), V, C, H * W, float(threshold), _dp(m))
+    return m
+
+
+def visual_hull(grid, rig, mask, *, step_vox=0.5):
+    inside = np.zeros(grid.shape_zyx, dtype=np.int32)
+    _check(lib().orc_visual_hull(ct.byref(_grid(grid)), _cams(rig), rig.n_views, float(step_vox),
+                                 _dp(_f64(mask)), inside.ctypes.data_as(ct.POINTER(ct.c_int32))),
+           "visual_hull")
+    return inside.astype(bool)
+
+
+def reconstruct_ext(grid, rig, frames, extinction, emission0, iters, *, step_vox=0.5, albedo=0.0,
+                    background=0.0, s_res=32, n_dirs=32, s_step=0.5, mode="sart", lam=1.0,
+                    clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, g_sigma=0.0, seed=0,
+                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0):
+    """Reconstruction with the paper's variants (flame mask, visual hull, gains
+    G(s), stop rule). Returns (emission, per-iteration image RMS, updates made)."""
+    F = _f64(frames)
+    em = np.array(emission0, dtype=np.float64, order="C", copy=True)
+    rp = _ReconParams()
+    rp.mode = {"sart": 0, "paper": 1, "mlem": 2}[mode]
+    rp.lam, rp.clamp_nonneg = float(lam), 1 if clamp_nonneg else 0
+    rp.alpha_l, rp.alpha_d, rp.tau = float(alpha_l), float(alpha_d), float(tau)
+    rp.g_sigma, rp.seed = float(g_sigma), int(seed)
+    rp.use_mask = 0 if flame_threshold is None else 1
+    rp.flame_threshold = 0.0 if flame_threshold is None else float(flame_threshold)
+    rp.use_hull, rp.outside_value, rp.stop_tol = 1 if hull else 0, float(outside_value), float(stop_tol)
+    res = np.zeros(max(iters, 1))
+    done = ct.c_int32()
+    _check(lib().orc_reconstruct_ext(ct.byref(_grid(grid)), _cams(rig), rig.n_views, em.shape[0],
+                                     float(step_vox), float(albedo), float(background), int(s_res),
+                                     int(n_dirs), float(s_step), _dp(F), _dp(_f64(extinction)),
+                                     _dp(em), int(iters), ct.byref(rp), _dp(res), ct.byref(done)),
+           "reconstruct_ext")
+    return em, res[:iters], int(done.value)

@@ -730,6 +730,269 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------- paper variants (f3) */
+
+/* Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds of two 32x32 -> 64-bit multiplies
+ * with the key bumped by the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n1 = lo1, n2 = hi0 ^ c[3] ^ k1, n3 = lo0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+/* G(s) of Eq. 11 for sample k of pixel `pix` of view v at iteration `it`:
+ * 1 + g_sigma * z, z standard normal by Box-Muller from the first two
+ * Philox words, u = (word + 1/2) / 2^32. */
+double orc_sample_gain(uint64_t seed, int32_t it, int32_t v, int64_t pix, int32_t k, double g_sigma)
+{
+    if (g_sigma == 0.0) return 1.0;
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)pix, (uint32_t)v, (uint32_t)it};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    orc_philox4x32_10(ctr, key, o);
+    double u1 = ((double)o[0] + 0.5) / 4294967296.0, u2 = ((double)o[1] + 0.5) / 4294967296.0;
+    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    return 1.0 + g_sigma * z;
+}
+
+/* Flame pixels (Sec. 4.1): a pixel is a flame pixel when any channel of the
+ * frame exceeds the threshold. frames [V][C][H][W], mask [V][H][W] (1 or 0). */
+void orc_flame_mask(const double *frames, int32_t V, int32_t C, long HW, double threshold, double *mask)
+{
+    for (int v = 0; v < V; ++v)
+        for (long p = 0; p < HW; ++p) {
+            double m = 0.0;
+            for (int c = 0; c < C; ++c)
+                if (frames[((long)v * C + c) * HW + p] > threshold) m = 1.0;
+            mask[(long)v * HW + p] = m;
+        }
+}
+
+/* Visual hull (Alg. 1): every flame ray of view v tags the key points around
+ * it -- the eight corners of every cell holding one of its samples -- with
+ * bit v; a key point is inside when it carries the bits of all views.
+ * mask [V][H][W], inside [N] (1 or 0). */
+int orc_visual_hull(const orc_grid *g, const orc_camera *cams, int32_t V, double step_vox, const double *mask,
+                    int32_t *inside)
+{
+    if (V > 64) return -1;
+    double ds = step_vox * grid_min_spacing(g);
+    long N = grid_nodes(g);
+    uint64_t *tag = (uint64_t *)calloc((size_t)N, sizeof(uint64_t));
+    if (!tag) return -2;
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        long HW = (long)c->width * c->height;
+        for (long p = 0; p < HW; ++p) {
+            if (mask[(long)v * HW + p] == 0.0) continue;
+            int u = (int)(p % c->width), vv = (int)(p / c->width);
+            double o[3], d[3], tn, tf;
+            camera_ray(c, u, vv, o, d);
+            if (!ray_box(g->lo, g->hi, o, d, &tn, &tf)) continue;
+            int K = n_segments(tn, tf, ds);
+            for (int k = 0; k < K; ++k) {
+                double t, len, x[3], q[3], w[8];
+                long idx[8];
+                segment(tn, tf, ds, k, &t, &len);
+                for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+                to_grid_coords(g, x, q);
+                stencil(g, q, idx, w, NULL, NULL);
+                for (int cr = 0; cr < 8; ++cr) tag[idx[cr]] |= (uint64_t)1 << v;
+            }
+        }
+    }
+    uint64_t all = V == 64 ? ~(uint64_t)0 : (((uint64_t)1 << V) - 1);
+    for (long j = 0; j < N; ++j) inside[j] = tag[j] == all;
+    free(tag);
+    return 0;
+}
+
+typedef struct {
+    int32_t mode;            /* 0 SART, 1 paper (Eq. 10-11), 2 EM */
+    double lambda;
+    int32_t clamp_nonneg;
+    double alpha_l, alpha_d, tau;
+    double g_sigma;          /* std of the gain G(s) of Eq. 11 (paper mode); 0: G = 1 */
+    uint64_t seed;
+    int32_t use_mask;        /* adjust with flame rays only */
+    double flame_threshold;
+    int32_t use_hull;        /* reconstruct key points inside the visual hull only */
+    double outside_value;    /* value given to key points outside the hull */
+    double stop_tol;         /* > 0: stop when successive image errors differ by less */
+} orc_recon_params;
+
+/* Paper-mode adjustment with per-sample gains and a ray mask (Eq. 10-12):
+ * the same as orc_backproject_paper with A_js multiplied by G(s) and rays
+ * with mask 0 skipped. */
+static int backproject_paper_ext(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C,
+                                 double step_vox, const orc_recon_params *rp, int32_t it,
+                                 const double *mask, const double *dL, double *delta)
+{
+    double ds = step_vox * grid_min_spacing(g);
+    long N = grid_nodes(g);
+    int nt = n_threads();
+    double *priv = alloc_private(nt, (long)C * N);
+    if (!priv) return -2;
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        long HW = (long)c->width * c->height;
+#pragma omp parallel num_threads(nt)
+        {
+            double *acc = priv + (long)thread_id() * C * N;
+#pragma omp for schedule(static)
+            for (long p = 0; p < HW; ++p) {
+                if (mask && mask[(long)v * HW + p] == 0.0) continue;
+                int u = (int)(p % c->width), vv = (int)(p / c->width);
+                double o[3], d[3], tn, tf;
+                camera_ray(c, u, vv, o, d);
+                if (!ray_box(g->lo, g->hi, o, d, &tn, &tf)) continue;
+                int K = n_segments(tn, tf, ds);
+                for (int k = 0; k < K; ++k) {
+                    double t, len, x[3], q[3], w[8], f[3];
+                    long idx[8];
+                    segment(tn, tf, ds, k, &t, &len);
+                    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+                    to_grid_coords(g, x, q);
+                    stencil(g, q, idx, w, f, NULL);
+                    double gain = orc_sample_gain(rp->seed, it, v, p, k, rp->g_sigma);
+                    double tr = pow(1.0 - rp->tau, (double)k);
+                    for (int cr = 0; cr < 8; ++cr) {
+                        double ddx = f[0] - (double)(cr & 1);
+                        double ddy = f[1] - (double)((cr >> 1) & 1);
+                        double ddz = f[2] - (double)((cr >> 2) & 1);
+                        double D = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+                        double a = gain * rp->alpha_l * tr * exp(-rp->alpha_d * D);
+                        for (int ch = 0; ch < C; ++ch)
+                            acc[(long)ch * N + idx[cr]] += a * dL[((long)v * C + ch) * HW + p];
+                    }
+                }
+            }
+        }
+    }
+    reduce_private(priv, nt, (long)C * N, delta);
+    free(priv);
+    return 0;
+}
+
+/* Reconstruction with the paper's variants on top of orc_reconstruct:
+ *  - flame mask (Sec. 4.1): only flame rays enter the adjustment (their rows
+ *    of A for SART / EM, including the column sums);
+ *  - visual hull (Alg. 1): key points outside keep outside_value and are never
+ *    adjusted;
+ *  - gain G(s) of Eq. 11 in paper mode;
+ *  - stop rule (Sec. 3): E_it = RMS of F - I over the adjusted pixels before
+ *    the update of iteration it; stop before updating when it >= 1 and
+ *    |E_{it-1} - E_it| < stop_tol.
+ * iters_done receives the number of updates made; resid_out[it] = E_it. */
+int orc_reconstruct_ext(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
+                        double albedo, double background, int32_t s_res, int32_t n_dirs, double s_step,
+                        const double *frames, const double *sig, double *em_io, int32_t iters,
+                        const orc_recon_params *rp, double *resid_out, int32_t *iters_done)
+{
+    long N = grid_nodes(g);
+    long HW = (long)cams[0].width * cams[0].height;
+    long NI = (long)V * C * HW;
+    double *img = (double *)malloc(sizeof(double) * NI);
+    double *y = (double *)malloc(sizeof(double) * NI);
+    double *delta = (double *)malloc(sizeof(double) * C * N);
+    double *rows = (double *)malloc(sizeof(double) * V * HW);
+    double *cols = (double *)malloc(sizeof(double) * N);
+    double *ones_n = (double *)malloc(sizeof(double) * N);
+    double *mask = (double *)malloc(sizeof(double) * V * HW);
+    int32_t *inside = (int32_t *)malloc(sizeof(int32_t) * N);
+    long M3 = (long)s_res * s_res * s_res;
+    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * C * M3) : NULL;
+    int rc = 0, done = 0;
+    double prev_err = 0.0;
+    if (!img || !y || !delta || !rows || !cols || !ones_n || !mask || !inside ||
+        (albedo != 0.0 && s_res >= 2 && !S)) { rc = -2; goto done; }
+    if (rp->use_mask) orc_flame_mask(frames, V, C, HW, rp->flame_threshold, mask);
+    else for (long i = 0; i < V * HW; ++i) mask[i] = 1.0;
+    if (rp->use_hull) {
+        rc = orc_visual_hull(g, cams, V, step_vox, mask, inside);
+        if (rc) goto done;
+        for (int ch = 0; ch < C; ++ch)
+            for (long j = 0; j < N; ++j)
+                if (!inside[j]) em_io[(long)ch * N + j] = rp->outside_value;
+    } else {
+        for (long j = 0; j < N; ++j) inside[j] = 1;
+    }
+    if (rp->mode == 0 || rp->mode == 2) {
+        for (long i = 0; i < N; ++i) ones_n[i] = 1.0;
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, rows, NULL);
+        if (rc) goto done;
+        rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, mask, cols);
+        if (rc) goto done;
+    }
+    for (int it = 0; it < iters; ++it) {
+        if (S) {
+            rc = orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
+            if (rc) goto done;
+        }
+        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, img, NULL);
+        if (rc) goto done;
+        double r2 = 0.0, cnt = 0.0;
+        for (int v = 0; v < V; ++v)
+            for (int ch = 0; ch < C; ++ch)
+                for (long p = 0; p < HW; ++p) {
+                    if (mask[(long)v * HW + p] == 0.0) continue;
+                    long i = ((long)v * C + ch) * HW + p;
+                    r2 += (frames[i] - img[i]) * (frames[i] - img[i]);
+                    cnt += 1.0;
+                }
+        double err = cnt > 0.0 ? sqrt(r2 / cnt) : 0.0;
+        if (resid_out) resid_out[it] = err;
+        if (rp->stop_tol > 0.0 && it >= 1 && fabs(prev_err - err) < rp->stop_tol) break;
+        prev_err = err;
+        for (int v = 0; v < V; ++v)
+            for (int ch = 0; ch < C; ++ch)
+                for (long p = 0; p < HW; ++p) {
+                    long i = ((long)v * C + ch) * HW + p;
+                    double m = mask[(long)v * HW + p];
+                    double R = rows[(long)v * HW + p];
+                    if (rp->mode == 0) y[i] = (m != 0.0 && R > 0.0) ? (frames[i] - img[i]) / R : 0.0;
+                    else if (rp->mode == 2) y[i] = (m != 0.0) ? (img[i] > 0.0 ? frames[i] / img[i] : 1.0) : 0.0;
+                    else y[i] = m != 0.0 ? frames[i] - img[i] : 0.0;
+                }
+        if (rp->mode == 1)
+            rc = backproject_paper_ext(g, cams, V, C, step_vox, rp, it, mask, y, delta);
+        else
+            rc = orc_backproject_adjoint(g, cams, V, C, step_vox, sig, y, delta);
+        if (rc) goto done;
+        for (int ch = 0; ch < C; ++ch)
+            for (long j = 0; j < N; ++j) {
+                if (!inside[j]) continue;
+                double e = em_io[(long)ch * N + j];
+                if (rp->mode == 1) {
+                    e += delta[(long)ch * N + j];
+                } else {
+                    if (!(cols[j] > 0.0)) continue;
+                    if (rp->mode == 0) e += rp->lambda * delta[(long)ch * N + j] / cols[j];
+                    else e *= 1.0 + rp->lambda * (delta[(long)ch * N + j] / cols[j] - 1.0);
+                }
+                if (rp->clamp_nonneg && e < 0.0) e = 0.0;
+                em_io[(long)ch * N + j] = e;
+            }
+        ++done;
+    }
+done:
+    if (iters_done) *iters_done = done;
+    free(img); free(y); free(delta); free(rows); free(cols); free(ones_n); free(mask); free(inside); free(S);
+    return rc;
+}
+
 /* --------------------------------------------------------- temperature */
 
 /* Planck's law (Eq. 13): spectral radiance of a black body at wavelength

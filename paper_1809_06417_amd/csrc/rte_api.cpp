@@ -167,7 +167,8 @@ std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, co
 }
 
 struct Sizes {
-    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, y, part, cols, lut, total;
+    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, y, part, cols, lut, mask, inside, err,
+        total;
     int part_acc, lut_cap;
 };
 
@@ -194,8 +195,11 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
+    s.mask = sizeof(float) * (size_t)d.n_rays;
+    s.inside = sizeof(int32_t) * (size_t)d.n_nodes;
+    s.err = sizeof(float2) * (size_t)d.n_tiles + 2 * sizeof(double);
     s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.scat_part + s.dirs +
-              s.y + s.part + s.cols + s.lut;
+              s.y + s.part + s.cols + s.lut + s.mask + s.inside + s.err;
     return s;
 }
 
@@ -286,9 +290,10 @@ void free_plan(rte_plan *p)
     for (auto e : p->event_pool) hipEventDestroy(e);
     void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
                     p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_scat_part, p->d_dirs, p->d_y, p->d_part,
-                    p->d_cols, p->d_lut};
+                    p->d_cols, p->d_lut, p->d_mask, p->d_inside, p->d_err, p->d_err_sum};
     for (void *b : bufs)
         if (b) hipFree(b);
+    if (p->h_err_sum) hipHostFree(p->h_err_sum);
     delete p;
 }
 
@@ -465,8 +470,13 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_scat_part, full.scat_part, acc)) ||
         (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
         (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
-        (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)))
+        (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)) ||
+        (rc = dev_alloc(&p->d_mask, full.mask, acc)) || (rc = dev_alloc(&p->d_inside, full.inside, acc)) ||
+        (rc = dev_alloc(&p->d_err, sizeof(float2) * (size_t)d.n_tiles, acc)) ||
+        (rc = dev_alloc(&p->d_err_sum, 2 * sizeof(double), acc)))
         return bail(rc);
+    if (hipHostMalloc((void **)&p->h_err_sum, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(RTE_ERR_HIP, "pinned host allocation failed"));
     // in-scatter directions: spherical Fibonacci, voxel units per world unit
     if (M) {
         std::vector<float4> dirs(kMaxDirs, make_float4(0.f, 0.f, 0.f, 0.f));
@@ -639,34 +649,98 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
     if (!std::isfinite(params->lambda)) return fail(RTE_ERR_INVALID_ARG, "lambda must be finite");
     if (upd == RTE_UPDATE_PAPER && !(params->tau >= 0.0f && params->tau < 1.0f))
         return fail(RTE_ERR_INVALID_ARG, "tau must be in [0, 1)");
+    if (!(params->g_sigma >= 0.0f) || !std::isfinite(params->g_sigma))
+        return fail(RTE_ERR_INVALID_ARG, "g_sigma must be finite and >= 0");
+    if (params->use_hull && plan->V > 64) return fail(RTE_ERR_UNSUPPORTED, "the visual hull supports at most 64 views");
+    if (!(params->stop_tol >= 0.0f)) return fail(RTE_ERR_INVALID_ARG, "stop_tol must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
+    plan->last_iters = 0;
+    plan->last_errors.clear();
     const int C = plan->params.channels;
     const bool scat = plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
+    const float *mask = params->use_mask ? plan->d_mask : nullptr;
+    const int32_t *inside = params->use_hull ? plan->d_inside : nullptr;
+    const bool stop = params->stop_tol > 0.0f;
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
+    if (params->use_mask)
+        RTE_LAUNCH(plan, RTE_KERNEL_PACK, s,
+                   rte::launch_flame_mask(plan, frames, C, params->flame_threshold, plan->d_mask, s));
+    if (params->use_hull) {
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_hull(plan, mask, plan->d_inside, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_apply_outside(plan, C, plan->d_inside, params->outside_value, s));
+    }
     if (upd != RTE_UPDATE_PAPER && iters > 0) {
-        // row sums come out of every render; column sums A^T 1 once per call
+        // row sums come out of every render; column sums A^T 1 (over the
+        // adjusted rays) once per call
         RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
         RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
-                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s));
+                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
         RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                    rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
     }
     const int epi = upd == RTE_UPDATE_SART ? rte::kEpiSart : (upd == RTE_UPDATE_MLEM ? rte::kEpiMlem : rte::kEpiPaper);
     const int gmode = upd == RTE_UPDATE_PAPER ? rte::kGatherPaper : rte::kGatherAdjoint;
     const int umode = upd == RTE_UPDATE_SART ? rte::kUpdSart : (upd == RTE_UPDATE_MLEM ? rte::kUpdMlem : rte::kUpdPaper);
+    double prev_err = 0.0;
     for (int it = 0; it < iters; ++it) {
         if (scat) RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, nullptr, s));
         RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
-                   rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s));
+                   rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s, nullptr, mask,
+                                      stop ? plan->d_err : nullptr));
+        if (stop) {
+            RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s, rte::launch_err_reduce(plan, plan->d_err_sum, s));
+            RTE_HIP(hipMemcpyAsync(plan->h_err_sum, plan->d_err_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            RTE_HIP(hipStreamSynchronize(s));
+            const double cnt = plan->h_err_sum[1];
+            const double err = cnt > 0.0 ? std::sqrt(plan->h_err_sum[0] / cnt) : 0.0;
+            plan->last_errors.push_back((float)err);
+            if (it >= 1 && std::fabs(prev_err - err) < (double)params->stop_tol) break;
+            prev_err = err;
+        }
         RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
-                   rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau, s));
+                   rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau, s,
+                                      nullptr, params->g_sigma, params->seed, it));
         RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                    rte::launch_update(plan, C, C, umode, params->lambda, params->clamp_nonneg, nullptr,
-                                      nullptr, 0, 0, s));
+                                      nullptr, 0, 0, s, nullptr, inside));
+        plan->last_iters = it + 1;
     }
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_unpack(plan, emission, C, s));
+    return ok();
+}
+
+int rte_reconstruct_stats(const rte_plan *plan, int32_t *iters_done, int32_t *n_errors, float *errors,
+                          int32_t max_errors)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (iters_done) *iters_done = plan->last_iters;
+    if (n_errors) *n_errors = (int32_t)plan->last_errors.size();
+    if (errors)
+        for (int i = 0; i < max_errors && i < (int)plan->last_errors.size(); ++i) errors[i] = plan->last_errors[i];
+    return ok();
+}
+
+int rte_flame_mask(rte_plan *plan, const float *frames, float threshold, float *mask, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!frames || !mask) return fail(RTE_ERR_INVALID_ARG, "null frames or mask");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_flame_mask(plan, frames, plan->params.channels, threshold, mask, s));
+    return ok();
+}
+
+int rte_visual_hull(rte_plan *plan, const float *mask, int32_t *inside, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!inside) return fail(RTE_ERR_INVALID_ARG, "null output");
+    if (plan->V > 64) return fail(RTE_ERR_UNSUPPORTED, "the visual hull supports at most 64 views");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_hull(plan, mask, inside, s));
     return ok();
 }
 

@@ -32,6 +32,7 @@ enum GatherMode : int {
     kGatherCols = 2,          // acc_0 += g * w
     kGatherPaper = 3,         // acc_c += alpha_l y_c (1-tau)^k exp(-alpha_d D)
     kGatherGrad = 4,          // acc_c += g * y_c * w ; acc_C += q * w
+    kGatherHull = 5,          // bit v set when a flame ray of view v has a sample in the cell
 };
 
 enum UpdateMode : int {
@@ -91,6 +92,13 @@ struct rte_plan {
     float *d_part = nullptr;        // per-cell corner partials [8][acc][cells]
     float *d_cols = nullptr;        // column sums A^T 1 [N]
     float *d_lut = nullptr;         // [3][lut_cap]
+    float *d_mask = nullptr;        // flame-pixel mask [V][H][W]
+    int32_t *d_inside = nullptr;    // visual-hull flag per key point [N]
+    float2 *d_err = nullptr;        // per-tile (squared residual, count) of the stop rule
+    double *d_err_sum = nullptr;    // reduced (sum, count)
+    double *h_err_sum = nullptr;    // pinned host copy
+    int last_iters = 0;             // updates made by the last reconstruction
+    std::vector<float> last_errors; // image RMS per iteration of the last reconstruction (stop rule)
     int lut_cap = 0;
     int part_acc = 0;               // accumulators per corner the partial buffer holds
     size_t device_bytes = 0;
@@ -121,15 +129,25 @@ hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipSt
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s, float *exit_T = nullptr);
+                         int frame_channel0, float *out, hipStream_t s, float *exit_T = nullptr,
+                         const float *mask = nullptr, float2 *err = nullptr);
 hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
                                 hipStream_t s);
 hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,
-                         float alpha_l, float alpha_d, float tau, hipStream_t s);
+                         float alpha_l, float alpha_d, float tau, hipStream_t s,
+                         const float *rowmask = nullptr, float g_sigma = 0.f, uint64_t seed = 0,
+                         int iteration = 0);
+hipError_t launch_flame_mask(const rte_plan *p, const float *frames, int frame_channels, float threshold,
+                             float *mask, hipStream_t s);
+hipError_t launch_hull(const rte_plan *p, const float *mask, int32_t *inside, hipStream_t s);
+hipError_t launch_apply_outside(const rte_plan *p, int channels, const int32_t *inside, float value,
+                                hipStream_t s);
+hipError_t launch_err_reduce(const rte_plan *p, double *out, hipStream_t s);
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s, float *out2 = nullptr);
+                         int fit_channel, hipStream_t s, float *out2 = nullptr,
+                         const int32_t *inside = nullptr);
 hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, float *sig_planar,
                            bool packed, int lut_size, int fit_channel, float sigma_max,
                            float soot_t0, float soot_span, float t_min, float t_max,

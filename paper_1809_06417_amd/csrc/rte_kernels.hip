@@ -148,6 +148,37 @@ __device__ __forceinline__ void corner_offsets(int nx, int nxy, int elem, int co
         coff[c] = ((c & 1) + ((c >> 1) & 1) * nx + ((c >> 2) & 1) * nxy) * elem;
 }
 
+// Philox-4x32-10 counter-based generator (Salmon et al., SC 2011).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Per-sample gain G(s) of Eq. 11: 1 + g_sigma * z, z standard normal by
+// Box-Muller from two Philox words keyed by the seed, counter (k, pixel,
+// view, iteration).
+__device__ __forceinline__ float sample_gain(uint32_t seed_lo, uint32_t seed_hi, int it, int v, int pix, int k,
+                                             float g_sigma)
+{
+    uint32_t c[4] = {(uint32_t)k, (uint32_t)pix, (uint32_t)v, (uint32_t)it};
+    philox4x32_10(c, seed_lo, seed_hi);
+    const float u1 = ((float)(c[0] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+    const float u2 = ((float)(c[1] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+    const float z = sqrtf(-2.0f * logf(u1)) * cosf(6.283185307179586f * u2);
+    return fmaf(g_sigma, z, 1.0f);
+}
+
 template <int C> struct Packed;
 template <> struct Packed<1> { using T = float2; };
 template <> struct Packed<3> { using T = float4; };
@@ -356,6 +387,8 @@ struct RenderArgs {
     float *out;
     float *g;
     float *exit_T;  // optional [V][H][W] transmittance at the exit (image renders)
+    const float *mask;   // optional [V][H][W] ray mask (1 adjust, 0 ignore) for residual epilogues
+    float2 *err;         // optional per-slot (sum of squared residuals, count) over masked pixels
     int fC, fc0;  // frames hold fC channels; channel c of the render reads fc0 + c
     int W, H, tiles_x, tiles_per_view, n_tiles, nb8;
     int nx, ny, nz, M;
@@ -380,12 +413,14 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-    if (px >= a.W || py >= a.H) return;
+    const bool in_image = px < a.W && py < a.H;
+    // lanes past the image edge stay for the tile's error butterfly only
+    if (!in_image && !(EPI >= kEpiSart && a.err)) return;
     const int HW = a.W * a.H;
-    const int pix = py * a.W + px;
+    const int pix = in_image ? py * a.W + px : 0;
     const int r = v * HW + pix;
     const float4 A = a.rayA[r], B = a.rayB[r];
-    const int K = __float_as_int(B.w);
+    const int K = in_image ? __float_as_int(B.w) : 0;
     const int nx = a.nx, nxy = a.nx * a.ny;
     constexpr int elem = C == 3 ? 16 : 8;
     const __amdgpu_buffer_rsrc_t vr = make_rsrc(a.vol, (int64_t)nxy * a.nz * elem);
@@ -452,28 +487,31 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
 #pragma unroll
         for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
         if (a.exit_T) a.exit_T[r] = T;
-    } else if constexpr (EPI == kEpiSart) {
+    } else if constexpr (EPI == kEpiSart || EPI == kEpiMlem || EPI == kEpiPaper) {
+        const float m = !in_image ? 0.0f : (a.mask ? a.mask[r] : 1.0f);
         const float inv = Rsum > 0.0f ? 1.0f / Rsum : 0.0f;
+        float r2 = 0.0f;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = (v * C + c) * HW + pix;
-            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
-            a.out[i] = (F - fmaf(T, a.background, I[c])) * inv;
-        }
-    } else if constexpr (EPI == kEpiMlem) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
+        for (int c = 0; c < C && in_image; ++c) {
             const int i = (v * C + c) * HW + pix;
             const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
             const float It = fmaf(T, a.background, I[c]);
-            a.out[i] = It > 0.0f ? F / It : 1.0f;
+            float yv;
+            if constexpr (EPI == kEpiSart) yv = (F - It) * inv;
+            else if constexpr (EPI == kEpiMlem) yv = It > 0.0f ? F / It : 1.0f;
+            else yv = F - It;
+            a.out[i] = m != 0.0f ? yv : 0.0f;
+            r2 = fmaf(F - It, F - It, r2);
         }
-    } else if constexpr (EPI == kEpiPaper) {
+        if (a.err) {
+            // fixed-order butterfly over the tile's 64 rays; lane 0 stores it
+            float e0 = m != 0.0f ? r2 : 0.0f, e1 = m != 0.0f ? (float)C : 0.0f;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = (v * C + c) * HW + pix;
-            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
-            a.out[i] = F - fmaf(T, a.background, I[c]);
+            for (int off = 32; off > 0; off >>= 1) {
+                e0 += __shfl_xor(e0, off, 64);
+                e1 += __shfl_xor(e1, off, 64);
+            }
+            if (lane == 0) a.err[slot] = make_float2(e0, e1);
         }
     }
 }
@@ -733,6 +771,10 @@ struct GatherArgs {
     int ncells;
     float ds, inv_ds;
     float alpha_l, alpha_d, log2_keep;  // paper mode
+    float g_sigma;                      // paper mode: spread of the gains G(s)
+    uint32_t seed_lo, seed_hi;
+    int iteration;
+    const float *rowmask;               // optional [V][H][W]: rays with 0 are skipped (cols, hull)
 };
 
 constexpr float kBoxPad = 1e-3f;   // voxels: cell box padding for FP32 sample positions
@@ -740,8 +782,9 @@ constexpr float kPixPad = 2e-3f;   // pixels: projection rounding allowance
 
 template <int C, int MODE>
 struct GatherAcc {
-    static constexpr int N =
-        MODE == kGatherCols ? 1 : ((MODE == kGatherAdjointCols || MODE == kGatherGrad) ? C + 1 : C);
+    static constexpr int N = MODE == kGatherCols ? 1
+                             : MODE == kGatherHull ? 2
+                             : ((MODE == kGatherAdjointCols || MODE == kGatherGrad) ? C + 1 : C);
 };
 
 // Each work-item owns one cell (voxel) c and gathers every sample that the
@@ -774,9 +817,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
     const float hi[3] = {(float)cx + 1.0f + kBoxPad, (float)cy + 1.0f + kBoxPad,
                          (float)cz + 1.0f + kBoxPad};
     const int HW = a.W * a.H;
+    uint64_t hull_bits = 0;
 
     for (int v = 0; v < a.V; ++v) {
         const float *P = a.proj[v].P;
+        bool found = false;  // hull mode: this view already tags the cell
         // project the 8 corners of the padded box
         float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
         bool behind = false;
@@ -803,10 +848,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
             v0 = max(v0, (int)ceilf(vmin - 0.5f - kPixPad));
             v1 = min(v1, (int)floorf(vmax - 0.5f + kPixPad));
         }
-        for (int py = v0; py <= v1; ++py) {
-            for (int px = u0; px <= u1; ++px) {
+        for (int py = v0; py <= v1 && !found; ++py) {
+            for (int px = u0; px <= u1 && !found; ++px) {
                 const int pix = py * a.W + px;
                 const int r = v * HW + pix;
+                if ((MODE == kGatherCols || MODE == kGatherHull) && a.rowmask && a.rowmask[r] == 0.0f) continue;
                 const float4 B = a.rayB[r];
                 const float4 A = a.rayA[r];
                 const int K = __float_as_int(B.w);
@@ -833,7 +879,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                 if (s_out >= (float)(K - 1) * a.ds) k_hi = K - 1;
                 if (k_lo > k_hi) continue;
                 float yv[C];
-                if constexpr (MODE != kGatherCols) {
+                if constexpr (MODE != kGatherCols && MODE != kGatherHull) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) yv[c] = a.y[(v * C + c) * HW + pix];
                 }
@@ -848,8 +894,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                     cell_of(fmaf(s, B.y, A.y), a.ny, iy, fy);
                     cell_of(fmaf(s, B.z, A.z), a.nz, iz, fz);
                     if (ix != cx || iy != cy || iz != cz) continue;
-                    if constexpr (MODE == kGatherPaper) {
-                        const float keep = exp2f((float)k * a.log2_keep);
+                    if constexpr (MODE == kGatherHull) {
+                        hull_bits |= (uint64_t)1 << v;
+                        found = true;
+                        break;
+                    } else if constexpr (MODE == kGatherPaper) {
+                        float keep = exp2f((float)k * a.log2_keep);
+                        if (a.g_sigma != 0.0f)
+                            keep *= sample_gain(a.seed_lo, a.seed_hi, a.iteration, v, pix, k, a.g_sigma);
 #pragma unroll
                         for (int c = 0; c < 8; ++c) {
                             const float ddx = fx - (float)(c & 1);
@@ -865,8 +917,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
                         float w[8];
                         tri_weights(fx, fy, fz, w);
                         if constexpr (MODE == kGatherCols) {
+                            const float gm = a.rowmask ? gk * a.rowmask[r] : gk;
 #pragma unroll
-                            for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gk, w[c], acc[c][0]);
+                            for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gm, w[c], acc[c][0]);
                         } else if constexpr (MODE == kGatherGrad) {
                             const float qk = a.q[(gp - a.g) + k * kTileRays];
                             float gy[C];
@@ -897,6 +950,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
     }
     // brick-major cell index: a wave stores 64 consecutive floats per plane
     const int cell = b * kBlock + threadIdx.x;
+    if constexpr (MODE == kGatherHull) {
+        a.part[cell] = __uint_as_float((uint32_t)hull_bits);
+        a.part[(int64_t)a.ncells + cell] = __uint_as_float((uint32_t)(hull_bits >> 32));
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c)
 #pragma unroll
@@ -911,6 +969,7 @@ struct UpdateArgs {
     float *cols;         // column sums (read, or written in kUpdCols)
     float *out;          // delta [C][N] (kUpdDelta, kUpdGrad)
     float *out2;         // extinction gradient [N] (kUpdGrad)
+    const int32_t *inside;  // optional: key points outside the visual hull are not updated
     float *temperature;  // kUpdTemp output
     const float *lut;    // [3][lut_cap]
     int lut_cap, lut_size, fit_channel;
@@ -977,6 +1036,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
         e = fminf(fmaxf(e, row[0]), row[a.lut_size - 1]);
         a.temperature[j] = lut_invert(row, a.lut_size, e, a.t_min, a.t_max);
     } else {
+        if (a.inside && !a.inside[j]) return;
         const float cs = (MODE == kUpdPaper) ? 1.0f : a.cols[j];
         if (MODE != kUpdPaper && !(cs > 0.0f)) return;
         float em[C];
@@ -1052,6 +1112,81 @@ __global__ __launch_bounds__(kBlock) void temp_invert_kernel(const float *e, flo
     if (j >= n) return;
     const float x = fminf(fmaxf(e[j], row[0]), row[L - 1]);
     T[j] = lut_invert(row, L, x, t_min, t_max);
+}
+
+// Flame pixels (Sec. 4.1): 1 where any channel of the frame exceeds the threshold.
+__global__ __launch_bounds__(kBlock) void flame_mask_kernel(const float *frames, int C, int V, int HW, float thr,
+                                                           float *mask)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= (int64_t)V * HW) return;
+    const int v = (int)(r / HW), pix = (int)(r - (int64_t)v * HW);
+    float m = 0.0f;
+    for (int c = 0; c < C; ++c)
+        if (frames[((int64_t)v * C + c) * HW + pix] > thr) m = 1.0f;
+    mask[r] = m;
+}
+
+// Visual hull (Alg. 1): a key point is inside when the eight cells around it
+// carry, together, the flame-ray bits of every view.
+__global__ __launch_bounds__(kBlock) void hull_assemble_kernel(const float *part, int ncells, int nx, int ny, int nz,
+                                                              int bx, int by, uint64_t all, int32_t *inside,
+                                                              int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int jx = (int)(j % nx), jy = (int)((j / nx) % ny), jz = (int)(j / ((int64_t)nx * ny));
+    uint64_t bits = 0;
+    for (int e = 0; e < 8; ++e) {
+        const int cx = jx - (e & 1), cy = jy - ((e >> 1) & 1), cz = jz - ((e >> 2) & 1);
+        if (cx < 0 || cy < 0 || cz < 0 || cx > nx - 2 || cy > ny - 2 || cz > nz - 2) continue;
+        const int brick = ((cz >> 2) * by + (cy >> 3)) * bx + (cx >> 3);
+        const int cell = brick * kBlock + (((cz & 3) * 8 + (cy & 7)) * 8 + (cx & 7));
+        bits |= (uint64_t)__float_as_uint(part[cell]) | ((uint64_t)__float_as_uint(part[(int64_t)ncells + cell]) << 32);
+    }
+    inside[j] = bits == all ? 1 : 0;
+}
+
+// Key points outside the hull take a fixed value in every emission channel.
+template <int C>
+__global__ __launch_bounds__(kBlock) void apply_outside_kernel(float *vol, const int32_t *inside, float value, int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n || inside[j]) return;
+    if constexpr (C == 3) {
+        float4 *p = reinterpret_cast<float4 *>(vol) + j;
+        p->x = value;
+        p->y = value;
+        p->z = value;
+    } else {
+        reinterpret_cast<float2 *>(vol)[j].x = value;
+    }
+}
+
+// Sum of the per-tile (squared residual, count) pairs in a fixed order, in
+// double precision: one block, strided partial sums, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void err_reduce_kernel(const float2 *err, int n, double *out)
+{
+    __shared__ double s0[kBlock], s1[kBlock];
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        a0 += (double)err[i].x;
+        a1 += (double)err[i].y;
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = s1[0];
+    }
 }
 
 static inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -1158,10 +1293,13 @@ static hipError_t render_dispatch(const RenderArgs &a, bool emis, bool scat, boo
 
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s, float *exit_T)
+                         int frame_channel0, float *out, hipStream_t s, float *exit_T, const float *mask,
+                         float2 *err)
 {
     RenderArgs a{};
     a.exit_T = exit_T;
+    a.mask = mask;
+    a.err = err;
     a.fC = frame_channels;
     a.fc0 = frame_channel0;
     a.rayA = p->d_rayA;
@@ -1180,7 +1318,8 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
     a.tile_order = p->d_tile_order;
     // an image needs every pixel (misses get the background); residuals and
     // weights are only ever read for rays that hold samples
-    a.n_launch = epilogue == kEpiImage ? p->n_tiles : p->n_active_tiles;
+    // (the image error of the stop rule also needs the pixels of empty tiles)
+    a.n_launch = (epilogue == kEpiImage || err) ? p->n_tiles : p->n_active_tiles;
     a.nb8 = (a.n_launch + 3) / 4;
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
@@ -1280,9 +1419,15 @@ static void gather_launch(const GatherArgs &a, hipStream_t s)
 }
 
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y, float alpha_l,
-                         float alpha_d, float tau, hipStream_t s)
+                         float alpha_d, float tau, hipStream_t s, const float *rowmask, float g_sigma,
+                         uint64_t seed, int iteration)
 {
     GatherArgs a{};
+    a.rowmask = rowmask;
+    a.g_sigma = g_sigma;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.iteration = iteration;
     a.rayA = p->d_rayA;
     a.rayB = p->d_rayB;
     a.tile_off = p->d_tile_off;
@@ -1316,6 +1461,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         case kGatherCols: gather_launch<3, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<3, kGatherPaper>(a, s); break;
         case kGatherGrad: gather_launch<3, kGatherGrad>(a, s); break;
+        case kGatherHull: gather_launch<3, kGatherHull>(a, s); break;
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -1325,6 +1471,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         case kGatherCols: gather_launch<1, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<1, kGatherPaper>(a, s); break;
         case kGatherGrad: gather_launch<1, kGatherGrad>(a, s); break;
+        case kGatherHull: gather_launch<1, kGatherHull>(a, s); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -1339,10 +1486,11 @@ static void update_launch(const UpdateArgs &a, hipStream_t s)
 
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s, float *out2)
+                         int fit_channel, hipStream_t s, float *out2, const int32_t *inside)
 {
     UpdateArgs a{};
     a.out2 = out2;
+    a.inside = inside;
     a.part = p->d_part;
     a.vol = p->d_vol;
     a.cols = p->d_cols;
@@ -1412,6 +1560,42 @@ hipError_t launch_temp_invert(const rte_plan *p, const float *e, float *T, int l
     hipLaunchKernelGGL(temp_invert_kernel, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, e, T,
                        p->d_lut + (size_t)fit_channel * p->lut_cap, lut_size, t_min, t_max,
                        p->n_nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_flame_mask(const rte_plan *p, const float *frames, int frame_channels, float threshold,
+                             float *mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(flame_mask_kernel, dim3(blocks_for(p->n_rays)), dim3(kBlock), 0, s, frames, frame_channels,
+                       p->V, p->W * p->H, threshold, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_hull(const rte_plan *p, const float *mask, int32_t *inside, hipStream_t s)
+{
+    hipError_t e = launch_gather(p, 1, kGatherHull, nullptr, 0.f, 0.f, 0.f, s, mask, 0.f, 0, 0);
+    if (e != hipSuccess) return e;
+    const uint64_t all = p->V == 64 ? ~(uint64_t)0 : (((uint64_t)1 << p->V) - 1);
+    hipLaunchKernelGGL(hull_assemble_kernel, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, p->d_part,
+                       (int)p->n_part_cells, p->grid.nx, p->grid.ny, p->grid.nz, (p->grid.nx - 1 + 7) / 8,
+                       (p->grid.ny - 1 + 7) / 8, all, inside, p->n_nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_outside(const rte_plan *p, int channels, const int32_t *inside, float value, hipStream_t s)
+{
+    if (channels == 3)
+        hipLaunchKernelGGL(apply_outside_kernel<3>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, p->d_vol, inside,
+                           value, p->n_nodes);
+    else
+        hipLaunchKernelGGL(apply_outside_kernel<1>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, p->d_vol, inside,
+                           value, p->n_nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_reduce(const rte_plan *p, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(err_reduce_kernel, dim3(1), dim3(kBlock), 0, s, p->d_err, p->n_tiles, out);
     return hipGetLastError();
 }
 

@@ -53,7 +53,10 @@ class RenderParams(ct.Structure):
 
 class ReconParams(ct.Structure):
     _fields_ = [("update", ct.c_int32), ("lam", ct.c_float), ("clamp_nonneg", ct.c_int32),
-                ("alpha_l", ct.c_float), ("alpha_d", ct.c_float), ("tau", ct.c_float)]
+                ("alpha_l", ct.c_float), ("alpha_d", ct.c_float), ("tau", ct.c_float),
+                ("g_sigma", ct.c_float), ("seed", ct.c_uint64), ("use_mask", ct.c_int32),
+                ("flame_threshold", ct.c_float), ("use_hull", ct.c_int32),
+                ("outside_value", ct.c_float), ("stop_tol", ct.c_float)]
 
 
 class _TempParams(ct.Structure):
@@ -116,6 +119,9 @@ def lib():
     L.rte_temperature_map.argtypes = [vp, vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_invert.argtypes = [vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_lut.argtypes = [vp, P(_TempParams), P(ct.c_float), i32]
+    L.rte_reconstruct_stats.argtypes = [vp, P(ct.c_int32), P(ct.c_int32), P(ct.c_float), i32]
+    L.rte_flame_mask.argtypes = [vp, vp, ct.c_float, vp, vp]
+    L.rte_visual_hull.argtypes = [vp, vp, vp, vp]
     L.rte_plan_set_timing.argtypes = [vp, i32]
     L.rte_plan_kernel_time.argtypes = [vp, i32, P(ct.c_double), P(ct.c_int64)]
     L.rte_last_error.restype = ct.c_char_p
@@ -278,7 +284,8 @@ class Plan:
                     tau=0.05, out=None):
         C = self.channels
         out = self._new((C,) + self.vol_shape) if out is None else out
-        rp = ReconParams(UPDATES["paper"], 1.0, 0, alpha_l, alpha_d, tau)
+        rp = ReconParams(update=UPDATES["paper"], lam=1.0, clamp_nonneg=0, alpha_l=alpha_l,
+                         alpha_d=alpha_d, tau=tau)
         _check(lib().rte_backproject(self._h, _ptr(extinction, self.vol_shape, "extinction"),
                                      _ptr(residual, self.img_shape(), "residual"),
                                      _ptr(out, (C,) + self.vol_shape, "delta"), BP_MODES[mode],
@@ -286,10 +293,17 @@ class Plan:
         return out
 
     def reconstruct(self, frames, extinction, emission, iters, update="sart", lam=1.0,
-                    clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05):
-        """In place on `emission` (warm start); returns it."""
+                    clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, g_sigma=0.0, seed=0,
+                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0):
+        """In place on `emission` (warm start); returns it. flame_threshold
+        (not None) restricts the adjustment to flame rays, hull=True to the
+        visual hull; stop_tol > 0 turns on the stop rule (see stats())."""
         C = self.channels
-        rp = ReconParams(UPDATES[update], lam, 1 if clamp_nonneg else 0, alpha_l, alpha_d, tau)
+        rp = ReconParams(update=UPDATES[update], lam=lam, clamp_nonneg=1 if clamp_nonneg else 0,
+                         alpha_l=alpha_l, alpha_d=alpha_d, tau=tau, g_sigma=g_sigma, seed=int(seed),
+                         use_mask=0 if flame_threshold is None else 1,
+                         flame_threshold=0.0 if flame_threshold is None else flame_threshold,
+                         use_hull=1 if hull else 0, outside_value=outside_value, stop_tol=stop_tol)
         _check(lib().rte_reconstruct(self._h, _ptr(frames, self.img_shape(), "frames"),
                                      _ptr(extinction, self.vol_shape, "extinction"),
                                      _ptr(emission, (C,) + self.vol_shape, "emission"), int(iters),
@@ -299,12 +313,32 @@ class Plan:
     def reconstruct_temperature(self, frames, temperature, iters, temp=None, lam=1.0):
         """In place on `temperature` [K]; frames are [V, 3, H, W]."""
         temp = temp or TempParams()
-        rp = ReconParams(UPDATES["mlem"], lam, 0, 0.0, 0.0, 0.0)
+        rp = ReconParams(update=UPDATES["mlem"], lam=lam)
         _check(lib().rte_reconstruct_temperature(
             self._h, _ptr(frames, (self.V, 3, self.H, self.W), "frames"),
             _ptr(temperature, self.vol_shape, "temperature"), int(iters), ct.byref(rp),
             ct.byref(temp.c()), _stream()))
         return temperature
+
+    def stats(self, max_errors=1024):
+        """(updates made, per-iteration image RMS) of the last reconstruct()."""
+        n, ne = ct.c_int32(), ct.c_int32()
+        errs = (ct.c_float * max_errors)()
+        _check(lib().rte_reconstruct_stats(self._h, ct.byref(n), ct.byref(ne), errs, max_errors))
+        return int(n.value), [float(errs[i]) for i in range(min(int(ne.value), max_errors))]
+
+    def flame_mask(self, frames, threshold):
+        m = self._new((self.V, self.H, self.W))
+        _check(lib().rte_flame_mask(self._h, _ptr(frames, self.img_shape(), "frames"),
+                                    float(threshold), _ptr(m), _stream()))
+        return m
+
+    def visual_hull(self, mask=None):
+        import torch
+        inside = self._new(self.vol_shape, torch.int32)
+        _check(lib().rte_visual_hull(self._h, _ptr(mask, (self.V, self.H, self.W), "mask"),
+                                     _ptr(inside), _stream()))
+        return inside
 
     def temperature_map(self, temperature, temp=None):
         temp = temp or TempParams()

@@ -1,0 +1,108 @@
+"""GPU parity of the paper's variants: flame mask (Sec. 4.1), visual hull
+(Alg. 1) with hull-restricted updates, the Gaussian gains G(s) of Eq. 11
+from the counter-based generator, and the stop rule (Sec. 3)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import VOLUME_RMS, as64, dev, f32, host, rel_rms, say
+from test_gpu_parity import STEP
+
+pytestmark = pytest.mark.gpu
+
+
+def rte():
+    from paper_1809_06417_amd import rte as _rte
+    return _rte
+
+
+def flame_case():
+    g, em, sig = synth.tiny_volume(seed=3, n=20)
+    rig = synth.ring_rig(6, 40, 36, elevation_jitter_deg=15, seed=5)
+    em, sig = f32(em), f32(sig)
+    F = f32(oracle.render(g, rig, as64(em), as64(sig)))
+    return g, rig, em, sig, F, float(np.float32(0.02 * F.max()))
+
+
+def test_flame_mask_bit_exact():
+    g, rig, em, sig, F, thr = flame_case()
+    say("flame mask")
+    with rte().Plan(g, rig, channels=1) as p:
+        m = host(p.flame_mask(dev(F), thr))
+    np.testing.assert_array_equal(m, oracle.flame_mask(as64(F), thr))
+
+
+def boundary(mask):
+    """Key points with a 6-neighbour of the other value."""
+    b = np.zeros_like(mask, dtype=bool)
+    for ax in range(3):
+        for sh in (1, -1):
+            b |= np.roll(mask, sh, axis=ax) != mask
+    return b
+
+
+def test_visual_hull_matches_oracle():
+    g, rig, em, sig, F, thr = flame_case()
+    mask = oracle.flame_mask(as64(F), thr)
+    ref = oracle.visual_hull(g, rig, mask, step_vox=STEP)
+    say("visual hull")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        inside = p.visual_hull(dev(mask)).cpu().numpy().astype(bool)
+        all_in = p.visual_hull(None).cpu().numpy().astype(bool)
+    diff = inside != ref
+    # a sample on a cell face may fall on either side under FP32 vs FP64
+    # rounding: any disagreement must sit on the hull's boundary
+    assert diff.sum() <= 0.002 * diff.size
+    assert not np.any(diff & ~boundary(ref))
+    assert ref.sum() > 0 and np.all(all_in[ref])
+
+
+@pytest.mark.parametrize("update", ["sart", "paper"])
+def test_masked_hull_reconstruction_matches_oracle(update):
+    g, rig, em, sig, F, thr = flame_case()
+    mask = oracle.flame_mask(as64(F), thr)
+    ref_in = oracle.visual_hull(g, rig, mask, step_vox=STEP)
+    ref, _, n_ref = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), np.zeros(em.shape), 5, step_vox=STEP,
+                                           mode=update, flame_threshold=thr, hull=True, outside_value=-1e-3,
+                                           clamp_nonneg=False)
+    say("masked hull reconstruction", update)
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 5, update=update,
+                               flame_threshold=thr, hull=True, outside_value=-1e-3, clamp_nonneg=False))
+        inside = p.visual_hull(p.flame_mask(dev(F), thr)).cpu().numpy().astype(bool)
+    same = inside == ref_in
+    assert np.all(x[0][~inside] == np.float32(-1e-3))
+    assert rel_rms(x[0][same], ref[0][same]) <= VOLUME_RMS
+
+
+def test_paper_gains_match_oracle():
+    g, rig, em, sig, F, thr = flame_case()
+    kw = dict(step_vox=STEP, mode="paper", g_sigma=0.3, seed=123456789012345)
+    ref, _, _ = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), np.zeros(em.shape), 3, **kw)
+    plain = oracle.reconstruct(g, rig, as64(F), as64(sig), np.zeros(em.shape), 3, step_vox=STEP, mode="paper")
+    say("paper gains")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 3, update="paper", g_sigma=0.3,
+                               seed=123456789012345))
+    assert rel_rms(ref, plain) > 10 * VOLUME_RMS  # the gains matter
+    assert rel_rms(x, ref) <= VOLUME_RMS
+
+
+def test_stop_rule_matches_oracle():
+    g, rig, em, sig, F, thr = flame_case()
+    _, errs, _ = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), np.zeros(em.shape), 12, step_vox=STEP)
+    d = np.abs(np.diff(errs))
+    # a tolerance well between two successive differences: no borderline decision
+    i = int(np.argmax(d[1:] < 0.5 * d[:-1])) + 1
+    tol = float(np.sqrt(d[i] * d[i - 1]))
+    ref, ref_err, n_ref = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), np.zeros(em.shape), 12,
+                                                 step_vox=STEP, stop_tol=tol)
+    assert 1 <= n_ref < 12
+    say("stop rule")
+    with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 12, stop_tol=tol))
+        n, gerr = p.stats()
+    assert n == n_ref
+    np.testing.assert_allclose(gerr, ref_err[:len(gerr)], rtol=1e-4)
+    assert rel_rms(x, ref) <= VOLUME_RMS
