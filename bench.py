@@ -5,10 +5,15 @@ A step is one iteration of the reconstruction loop over the whole workload
 back-projection, update). Inputs are seeded synthetic volumes and camera
 rings, resident in HBM before timing starts.
 
-  python bench.py [--steps K] [--warmup W] [--workload colour|temperature|tiny]
+  python bench.py [--steps K] [--warmup W] [--workload colour|temperature|tiny|diff|serve]
 
 Prints one JSON line. The metric is march samples per second (sum over all
 pixel rays of their segment counts, times iterations, over wall time).
+
+The serve workload is a stream of per-frame jobs (10 SART iterations each)
+from six seeded flame videos arriving at Poisson times; there a step is one
+job, --steps the number of jobs, and the line adds p50/p99 latency and
+frames/s of the continuous-batching loop and of one job at a time.
 """
 from __future__ import annotations
 
@@ -42,6 +47,10 @@ WORKLOADS = {
     # gradient-based reconstruction: one step = forward march + adjoint march +
     # gradient gather + Adam update of (emission, extinction)
     "diff": dict(n=256, views=12, W=1024, H=768, C=3, albedo=0.3, M=32, dirs=32, iters=50),
+    # grids, views and image sizes drawn per video (64-256^3, 4-12 views,
+    # 256^2-1024x768), 3 channels, no scattering
+    "serve": dict(n=0, views=0, W=0, H=0, C=3, albedo=0.0, M=0, dirs=32, iters=10,
+                  videos=6, rate=40.0),
 }
 
 
@@ -95,15 +104,18 @@ def cpu_baseline(g, rig, em, sig, frames, wl, views):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None, help="iterations (jobs for serve); default 20 (300)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="colour", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--hbm-budget-gib", type=int, default=64, help="serve: workspace budget for resident plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 300 if args.workload == "serve" else 20
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * 2**20 // 4
@@ -127,6 +139,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     wl = WORKLOADS[args.workload]
+    if args.workload == "serve":
+        return run_serve(args, wl)
     print(f"[bench] workload {args.workload}: building inputs", file=sys.stderr, flush=True)
     if args.workload in ("colour", "diff"):
         g, em, sig = synth.colour_volume(args.seed, n=wl["n"])
@@ -248,6 +262,123 @@ def main():
     }
     print(json.dumps(out))
     plan.close()
+
+
+def run_serve(args, wl):
+    """Serving: jobs arrive at Poisson times; the continuous-batching loop runs
+    them, then the same jobs run one at a time for comparison."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1809_06417_amd import rte, serve
+
+    n_jobs = args.steps
+    arrivals = synth.poisson_arrivals(n_jobs, wl["rate"], seed=args.seed)
+    vids = np.random.default_rng([args.seed, 1]).integers(0, wl["videos"], size=n_jobs)
+    specs = {v: synth.video_spec(v, seed=args.seed) for v in range(wl["videos"])}
+    print(f"[bench] serve: {n_jobs} jobs, {wl['videos']} videos, generating frames", file=sys.stderr, flush=True)
+    inputs, frame_of = {}, []
+    count = {}
+    samples_of = {}
+    for v, spec in specs.items():
+        with rte.Plan(spec.grid, spec.rig, channels=wl["C"]) as p:
+            samples_of[v] = p.samples
+            nf = int((vids == v).sum())
+            for fr in range(nf):
+                em, sig = synth.video_frame(spec, fr, device="cuda")
+                inputs[(v, fr)] = (p.render(em, sig), sig)
+            torch.cuda.synchronize()
+    for v in vids:
+        fr = count.get(int(v), 0)
+        count[int(v)] = fr + 1
+        frame_of.append(fr)
+    input_bytes = sum(F.numel() * 4 + s_.numel() * 4 for F, s_ in inputs.values())
+    print(f"[bench] inputs: {input_bytes / 2**30:.1f} GiB resident", file=sys.stderr, flush=True)
+
+    def make_jobs():
+        return [serve.Job(i, int(v), frame_of[i], float(t), *inputs[(int(v), frame_of[i])])
+                for i, (t, v) in enumerate(zip(arrivals, vids))]
+
+    budget = args.hbm_budget_gib << 30
+    videos = {v: serve.VideoState(s, channels=wl["C"]) for v, s in specs.items()}
+    # warmup: one job per video through the batched path (loads the kernels)
+    warm = [serve.Job(i, v, 0, 0.0, *inputs[(v, 0)]) for i, v in enumerate(sorted(set(int(x) for x in vids)))]
+    serve.serve(videos, warm, iters=min(args.warmup, wl["iters"]) or 1, hbm_budget_bytes=budget)
+    for vs in videos.values():
+        vs.volume = None
+        vs.resident = False
+        vs.busy = False
+    torch.cuda.synchronize()
+    for vs in videos.values():
+        if vs.plan is not None:
+            vs.plan.set_timing(True)
+    print("[bench] serving", file=sys.stderr, flush=True)
+    jobs = serve.serve(videos, make_jobs(), iters=wl["iters"], hbm_budget_bytes=budget,
+                       log=lambda m: None)
+    torch.cuda.synchronize()
+    summ = serve.latency_summary(jobs)
+    ktimes = {k: [0.0, 0] for k in rte.KERNELS}
+    for vs in videos.values():
+        if vs.plan is not None:
+            for k in rte.KERNELS:
+                ms, n = vs.plan.kernel_time(k)
+                ktimes[k][0] += ms
+                ktimes[k][1] += n
+            vs.plan.set_timing(False)
+    plans_resident = sum(vs.plan is not None for vs in videos.values())
+    for vs in videos.values():
+        vs.evict()
+    print(f"[bench] batched: {summ}", file=sys.stderr, flush=True)
+
+    print("[bench] one job at a time", file=sys.stderr, flush=True)
+    seq_videos = {v: serve.VideoState(s, channels=wl["C"]) for v, s in specs.items()}
+    seq = serve.serve_sequential(seq_videos, make_jobs(), iters=wl["iters"])
+    seq_summ = serve.latency_summary(seq)
+    for vs in seq_videos.values():
+        vs.evict()
+    print(f"[bench] sequential: {seq_summ}", file=sys.stderr, flush=True)
+
+    total_samples = sum(samples_of[int(v)] for v in vids) * wl["iters"]
+    offered = float(np.mean([samples_of[int(v)] for v in vids])) * wl["iters"] * wl["rate"]
+    value = total_samples / summ["span_s"]
+    b_render, b_gather = bytes_per_sample(wl["C"], False)
+    cands = {"render": b_render, "gather": b_gather}
+    dom = max(cands, key=lambda k: ktimes[k][0])
+    # aggregated over every batched launch: algorithmic bytes / kernel time
+    achieved = cands[dom] * total_samples / (ktimes[dom][0] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom + " (batched)",
+                "bytes_per_sample": cands[dom], "launches": ktimes[dom][1],
+                "avg_ms": ktimes[dom][0] / max(ktimes[dom][1], 1)}
+    per_kernel = {k: {"avg_ms": ms / n, "launches": n, "total_ms": ms} for k, (ms, n) in ktimes.items() if n}
+    out = {
+        "metric": "ray samples/s per render+backproject iteration",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": n_jobs,
+        "warmup": len(warm),
+        "ms_per_step": summ["span_s"] / n_jobs * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve: {n_jobs} frame jobs from {wl['videos']} seeded videos "
+                               f"(grids 64-256^3, 4-12 views, 256^2-1024x768, RGB, no scattering), "
+                               f"Poisson arrivals at {wl['rate']:g} jobs/s, {wl['iters']} SART iterations "
+                               f"per job warm-started from the resident previous volume",
+                   "videos": {v: f"{s.grid.nx}^3, {s.rig.n_views} views of {s.rig.width}x{s.rig.height}, "
+                                 f"{samples_of[v]} samples/iteration" for v, s in specs.items()},
+                   "hbm_budget_gib": args.hbm_budget_gib, "plans_resident": plans_resident,
+                   "offered_samples_per_s": offered, "utilisation": value / offered},
+        "serving": {"batched": summ, "one_at_a_time": seq_summ},
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "kernels": per_kernel,
+    }
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -250,6 +250,33 @@ int rte_backproject(rte_plan *plan, const float *extinction, const float *residu
 int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction, float *emission,
                     int32_t iters, const rte_recon_params *params, void *stream);
 
+/* Jobs: the reconstruction loop of rte_reconstruct split so that several
+ * plans can advance together, one iteration at a time (used by the serving
+ * loop; continuous batching at iteration granularity).
+ *
+ * rte_job_begin opens a job on a plan: uploads the start volume -- or, with
+ * emission == NULL, keeps the emission already resident in the plan from its
+ * previous job (warm start) -- and the frame's extinction, and prepares the
+ * flame mask, visual hull and column sums as rte_reconstruct does. frames
+ * [V][C][H][W] stays owned by the caller and must stay valid until
+ * rte_job_end. params->stop_tol must be 0.
+ * rte_job_step advances every listed plan (1..64 distinct plans with open
+ * jobs, one channel count, update rule and scattering setting) by one
+ * iteration with one launch per phase covering all of them; each plan's
+ * result is bitwise the one it would get alone. The launch arguments go
+ * through a staging buffer of the first plan: issue all steps that share a
+ * first plan on one stream. With timing on, the three batched launches are
+ * charged to the first plan (RTE_KERNEL_RENDER, _GATHER, _UPDATE).
+ * Errors: RTE_ERR_INVALID_ARG for a plan without an open job or listed twice,
+ * RTE_ERR_UNSUPPORTED for more than 64 plans or mixed settings; no plan is
+ * advanced then.
+ * rte_job_end copies the result to emission [C][nz][ny][nx] (may be NULL;
+ * the volume also stays resident in the plan) and closes the job. */
+int rte_job_begin(rte_plan *plan, const float *frames, const float *extinction, const float *emission,
+                  const rte_recon_params *params, void *stream);
+int rte_job_step(rte_plan *const *plans, int32_t n, void *stream);
+int rte_job_end(rte_plan *plan, float *emission, void *stream);
+
 /* Updates made by the last rte_reconstruct on this plan and, when its stop
  * rule was on, the image RMS of each rendered iteration: n_errors receives
  * how many were recorded, at most max_errors are copied to errors (either

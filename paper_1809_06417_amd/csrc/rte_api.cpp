@@ -39,6 +39,8 @@ int ok()
     } while (0)
 
 constexpr int kMaxLut = 65536;
+constexpr int kMaxBatch = 64;          // plans per rte_job_step
+constexpr size_t kBatchBytes = 1 << 17; // staging for their launch arguments
 constexpr int kMaxDirs = 256;
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -197,7 +199,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
     s.mask = sizeof(float) * (size_t)d.n_rays;
     s.inside = sizeof(int32_t) * (size_t)d.n_nodes;
-    s.err = sizeof(float2) * (size_t)d.n_tiles + 2 * sizeof(double);
+    s.err = sizeof(float2) * (size_t)d.n_tiles + 2 * sizeof(double) + kBatchBytes;
     s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.scat_part + s.dirs +
               s.y + s.part + s.cols + s.lut + s.mask + s.inside + s.err;
     return s;
@@ -294,6 +296,9 @@ void free_plan(rte_plan *p)
     for (void *b : bufs)
         if (b) hipFree(b);
     if (p->h_err_sum) hipHostFree(p->h_err_sum);
+    if (p->h_batch) hipHostFree(p->h_batch);
+    if (p->batch_event) hipEventDestroy(p->batch_event);
+    if (p->d_batch) hipFree(p->d_batch);
     delete p;
 }
 
@@ -475,7 +480,12 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         (rc = dev_alloc(&p->d_err, sizeof(float2) * (size_t)d.n_tiles, acc)) ||
         (rc = dev_alloc(&p->d_err_sum, 2 * sizeof(double), acc)))
         return bail(rc);
-    if (hipHostMalloc((void **)&p->h_err_sum, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if ((rc = dev_alloc(&p->d_batch, kBatchBytes, acc))) return bail(rc);
+    p->batch_bytes = kBatchBytes;
+    if (hipHostMalloc((void **)&p->h_err_sum, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&p->h_batch, kBatchBytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&p->batch_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(p->batch_event, s) != hipSuccess)
         return bail(fail(RTE_ERR_HIP, "pinned host allocation failed"));
     // in-scatter directions: spherical Fibonacci, voxel units per world unit
     if (M) {
@@ -741,6 +751,106 @@ int rte_visual_hull(rte_plan *plan, const float *mask, int32_t *inside, void *st
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
     RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_hull(plan, mask, inside, s));
+    return ok();
+}
+
+int rte_job_begin(rte_plan *plan, const float *frames, const float *extinction, const float *emission,
+                  const rte_recon_params *params, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!frames || !extinction || !params) return fail(RTE_ERR_INVALID_ARG, "null frames, extinction or params");
+    if (plan->job_open) return fail(RTE_ERR_INVALID_ARG, "the plan already has an open job");
+    const int upd = params->update;
+    if (upd != RTE_UPDATE_SART && upd != RTE_UPDATE_PAPER && upd != RTE_UPDATE_MLEM)
+        return fail(RTE_ERR_INVALID_ARG, "unknown update rule %d", upd);
+    if (!std::isfinite(params->lambda) || !(params->g_sigma >= 0.0f))
+        return fail(RTE_ERR_INVALID_ARG, "lambda must be finite and g_sigma >= 0");
+    if (upd == RTE_UPDATE_PAPER && !(params->tau >= 0.0f && params->tau < 1.0f))
+        return fail(RTE_ERR_INVALID_ARG, "tau must be in [0, 1)");
+    if (params->stop_tol != 0.0f) return fail(RTE_ERR_UNSUPPORTED, "jobs run a fixed number of steps (stop_tol = 0)");
+    if (params->use_hull && plan->V > 64) return fail(RTE_ERR_UNSUPPORTED, "the visual hull supports at most 64 views");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    const int C = plan->params.channels;
+    const float *mask = params->use_mask ? plan->d_mask : nullptr;
+    // emission == NULL: warm start from the volume resident in the plan
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s, emission == nullptr));
+    if (params->use_mask)
+        RTE_LAUNCH(plan, RTE_KERNEL_PACK, s,
+                   rte::launch_flame_mask(plan, frames, C, params->flame_threshold, plan->d_mask, s));
+    if (params->use_hull) {
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_hull(plan, mask, plan->d_inside, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_apply_outside(plan, C, plan->d_inside, params->outside_value, s));
+    }
+    if (upd != RTE_UPDATE_PAPER) {
+        RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
+                   rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
+                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
+        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                   rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
+    }
+    plan->job_open = true;
+    plan->job_frames = frames;
+    plan->job_params = *params;
+    plan->job_iter = 0;
+    return ok();
+}
+
+int rte_job_step(rte_plan *const *plans, int32_t n, void *stream)
+{
+    if (!plans || n < 1) return fail(RTE_ERR_INVALID_ARG, "need at least one plan");
+    if (n > kMaxBatch) return fail(RTE_ERR_UNSUPPORTED, "at most %d plans per step", kMaxBatch);
+    const rte_plan *p0 = plans[0];
+    for (int i = 0; i < n; ++i) {
+        const rte_plan *p = plans[i];
+        if (!p || !p->job_open) return fail(RTE_ERR_INVALID_ARG, "plan %d has no open job", i);
+        for (int k = 0; k < i; ++k)
+            if (plans[k] == p) return fail(RTE_ERR_INVALID_ARG, "plan %d appears twice", i);
+        if (p->params.channels != p0->params.channels || p->job_params.update != p0->job_params.update ||
+            (p->params.albedo > 0.0f) != (p0->params.albedo > 0.0f))
+            return fail(RTE_ERR_UNSUPPORTED, "a step batches plans with one channel count, update rule and scattering setting");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool scat = p0->params.albedo > 0.0f && p0->params.scatter_res >= 2;
+    if (scat)
+        for (int i = 0; i < n; ++i) RTE_LAUNCH(plans[i], RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plans[i], nullptr, s));
+    // timing of the batched launches is charged to the first plan
+    rte_plan *p0t = plans[0];
+    hipEvent_t marks[6] = {};
+    if (p0t->timing)
+        for (auto &m : marks) m = take_event(p0t);
+    hipError_t e = rte::launch_step_batch(plans, n, s, p0t->timing ? marks : nullptr);
+    if (p0t->timing) {
+        const int kid[3] = {RTE_KERNEL_RENDER, RTE_KERNEL_GATHER, RTE_KERNEL_UPDATE};
+        for (int k = 0; k < 3; ++k) {
+            if (marks[2 * k] && marks[2 * k + 1]) {
+                p0t->pending.push_back({kid[k], marks[2 * k], marks[2 * k + 1]});
+            } else {
+                if (marks[2 * k]) p0t->event_pool.push_back(marks[2 * k]);
+                if (marks[2 * k + 1]) p0t->event_pool.push_back(marks[2 * k + 1]);
+            }
+        }
+    }
+    if (e != hipSuccess) return fail(RTE_ERR_HIP, "batched step failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        plans[i]->job_iter += 1;
+        plans[i]->last_stream = s;
+    }
+    return ok();
+}
+
+int rte_job_end(rte_plan *plan, float *emission, void *stream)
+{
+    if (int rc = check_plan(plan)) return rc;
+    if (!plan->job_open) return fail(RTE_ERR_INVALID_ARG, "the plan has no open job");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->last_stream = s;
+    if (emission) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_unpack(plan, emission, plan->params.channels, s));
+    plan->last_iters = plan->job_iter;
+    plan->job_open = false;
+    plan->job_frames = nullptr;
     return ok();
 }
 

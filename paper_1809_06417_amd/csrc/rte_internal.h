@@ -98,6 +98,15 @@ struct rte_plan {
     double *d_err_sum = nullptr;    // reduced (sum, count)
     double *h_err_sum = nullptr;    // pinned host copy
     int last_iters = 0;             // updates made by the last reconstruction
+    // open job (rte_job_begin .. rte_job_end)
+    bool job_open = false;
+    const float *job_frames = nullptr;
+    rte_recon_params job_params{};
+    int job_iter = 0;
+    void *d_batch = nullptr;        // device copy of batched launch arguments
+    void *h_batch = nullptr;        // pinned host staging of the same
+    hipEvent_t batch_event = nullptr;  // marks the end of the last upload from h_batch
+    size_t batch_bytes = 0;
     std::vector<float> last_errors; // image RMS per iteration of the last reconstruction (stop rule)
     int lut_cap = 0;
     int part_acc = 0;               // accumulators per corner the partial buffer holds
@@ -124,7 +133,10 @@ hipError_t launch_tile_kmax(const rte_plan *p, hipStream_t s);
 hipError_t launch_ray_export(const rte_plan *p, float *t_near, float *t_far, int32_t *nseg,
                              hipStream_t s);
 hipError_t launch_pack(const rte_plan *p, const float *emission, const float *extinction,
-                       int channels, hipStream_t s);
+                       int channels, hipStream_t s, bool keep_emission = false);
+// One iteration of every plan's open job: batched render, gather and update
+// launches. marks: NULL or 6 events recorded around the three launches.
+hipError_t launch_step_batch(rte_plan *const *plans, int n, hipStream_t s, hipEvent_t *marks = nullptr);
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s);
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,

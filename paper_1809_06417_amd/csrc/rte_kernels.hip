@@ -18,6 +18,8 @@
 // No float atomics anywhere: every sum has a fixed order, so results are
 // bitwise reproducible run to run.
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "rte_internal.h"
 
@@ -324,6 +326,7 @@ struct PackArgs {
     const float *em, *sig;
     float *vol;
     int64_t n;
+    int keep_emission;  // 1: only the extinction slot is written (warm start)
 };
 
 template <int C>
@@ -332,6 +335,11 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(PackArgs a)
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= a.n) return;
     const float s = a.sig ? a.sig[j] : 0.0f;
+    if (a.keep_emission) {
+        if constexpr (C == 3) reinterpret_cast<float4 *>(a.vol)[j].w = s;
+        else reinterpret_cast<float2 *>(a.vol)[j].y = s;
+        return;
+    }
     if constexpr (C == 3) {
         float4 v = make_float4(0.f, 0.f, 0.f, s);
         if (a.em) {
@@ -404,10 +412,10 @@ struct RenderArgs {
 // EMIS: read the emission (false: weights only). SCAT: add in-scattering.
 // WRITE_G: store the per-sample weight g_k = T_k Delta_k phi_k.
 template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
-__global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
+__device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
+    const int slot = blk * 4 + wave;
     if (slot >= a.n_launch) return;
     const int tile = a.tile_order[slot];
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
@@ -514,6 +522,28 @@ __global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
             if (lane == 0) a.err[slot] = make_float2(e0, e1);
         }
     }
+}
+
+template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
+__global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
+{
+    render_body<C, EMIS, SCAT, WRITE_G, EPI>(a, blockIdx.x);
+}
+
+// Job of a block in a batched launch: prefix[j] is the first block of job j.
+__device__ __forceinline__ int batch_job(const int *prefix, int n, int b)
+{
+    int j = 0;
+    while (j + 1 < n && prefix[j + 1] <= b) ++j;
+    return j;
+}
+
+// One launch covering the tiles of several independent jobs (plans).
+template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
+__global__ __launch_bounds__(kBlock) void render_batch_kernel(const RenderArgs *args, const int *prefix, int n)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    render_body<C, EMIS, SCAT, WRITE_G, EPI>(args[j], blockIdx.x - prefix[j]);
 }
 
 // --------------------------------------------------------- K6 adjoint march
@@ -796,10 +826,9 @@ struct GatherAcc {
 // cell's 8 corners. Sums run in a fixed order: views, then pixels row-major,
 // then samples.
 template <int C, int MODE>
-__global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
+__device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
 {
     constexpr int NA = GatherAcc<C, MODE>::N;
-    const int b = xcd_remap(blockIdx.x, a.nb8);
     if (b >= a.bx * a.by * a.bz) return;
     const int bxi = b % a.bx, byi = (b / a.bx) % a.by, bzi = b / (a.bx * a.by);
     const int cx = bxi * 8 + (threadIdx.x & 7);
@@ -961,6 +990,19 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
         for (int q = 0; q < NA; ++q) a.part[(int64_t)(c * NA + q) * a.ncells + cell] = acc[c][q];
 }
 
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
+{
+    gather_body<C, MODE>(a, xcd_remap(blockIdx.x, a.nb8));
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void gather_batch_kernel(const GatherArgs *args, const int *prefix, int n)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    gather_body<C, MODE>(args[j], blockIdx.x - prefix[j]);
+}
+
 // -------------------------------------------------------- assembly + update
 
 struct UpdateArgs {
@@ -999,9 +1041,9 @@ __device__ __forceinline__ float lut_invert(const float *row, int L, float x, fl
 // Sum the 8 cells around key point j (fixed order: corner index of j in the
 // cell = dx + 2 dy + 4 dz) and apply the update rule.
 template <int C, int MODE>
-__global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
+__device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
 {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t j = (int64_t)blk * kBlock + threadIdx.x;
     if (j >= a.n) return;
     const int jx = (int)(j % a.nx), jy = (int)((j / a.nx) % a.ny), jz = (int)(j / ((int64_t)a.nx * a.ny));
     constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : (MODE == kUpdGrad ? C + 1 : C));
@@ -1066,6 +1108,19 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
             reinterpret_cast<float2 *>(a.vol)[j].x = em[0];
         }
     }
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a)
+{
+    update_body<C, MODE>(a, blockIdx.x);
+}
+
+template <int C, int MODE>
+__global__ __launch_bounds__(kBlock) void update_batch_kernel(const UpdateArgs *args, const int *prefix, int n)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    update_body<C, MODE>(args[j], blockIdx.x - prefix[j]);
 }
 
 // ------------------------------------------------------- K5 temperature map
@@ -1231,9 +1286,9 @@ hipError_t launch_ray_export(const rte_plan *p, float *t_near, float *t_far, int
 }
 
 hipError_t launch_pack(const rte_plan *p, const float *emission, const float *extinction,
-                       int channels, hipStream_t s)
+                       int channels, hipStream_t s, bool keep_emission)
 {
-    PackArgs a{emission, extinction, p->d_vol, p->n_nodes};
+    PackArgs a{emission, extinction, p->d_vol, p->n_nodes, keep_emission ? 1 : 0};
     if (channels == 3)
         hipLaunchKernelGGL(pack_kernel<3>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a);
     else
@@ -1243,7 +1298,7 @@ hipError_t launch_pack(const rte_plan *p, const float *emission, const float *ex
 
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s)
 {
-    PackArgs a{nullptr, nullptr, p->d_vol, p->n_nodes};
+    PackArgs a{nullptr, nullptr, p->d_vol, p->n_nodes, 0};
     if (channels == 3)
         hipLaunchKernelGGL(unpack_kernel<3>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a, emission);
     else
@@ -1291,10 +1346,8 @@ static hipError_t render_dispatch(const RenderArgs &a, bool emis, bool scat, boo
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
-                         bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s, float *exit_T, const float *mask,
-                         float2 *err)
+static RenderArgs render_args(const rte_plan *p, int epilogue, const float *frames, int frame_channels,
+                              int frame_channel0, float *out, float *exit_T, const float *mask, float2 *err)
 {
     RenderArgs a{};
     a.exit_T = exit_T;
@@ -1331,6 +1384,15 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
     const int n[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
     for (int i = 0; i < 3; ++i)
         a.s_scale[i] = a.M >= 2 ? (float)((double)(a.M - 1) / (double)(n[i] - 1)) : 0.0f;
+    return a;
+}
+
+hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
+                         bool write_g, int epilogue, const float *frames, int frame_channels,
+                         int frame_channel0, float *out, hipStream_t s, float *exit_T, const float *mask,
+                         float2 *err)
+{
+    const RenderArgs a = render_args(p, epilogue, frames, frame_channels, frame_channel0, out, exit_T, mask, err);
     if (channels == 3) return render_dispatch<3>(a, use_emission, use_scatter, write_g, epilogue, s);
     return render_dispatch<1>(a, use_emission, use_scatter, write_g, epilogue, s);
 }
@@ -1418,9 +1480,8 @@ static void gather_launch(const GatherArgs &a, hipStream_t s)
     hipLaunchKernelGGL((gather_kernel<C, MODE>), dim3(a.nb8), dim3(kBlock), 0, s, a);
 }
 
-hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y, float alpha_l,
-                         float alpha_d, float tau, hipStream_t s, const float *rowmask, float g_sigma,
-                         uint64_t seed, int iteration)
+static GatherArgs gather_args(const rte_plan *p, const float *y, float alpha_l, float alpha_d, float tau,
+                              const float *rowmask, float g_sigma, uint64_t seed, int iteration)
 {
     GatherArgs a{};
     a.rowmask = rowmask;
@@ -1454,6 +1515,14 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
     a.alpha_l = alpha_l;
     a.alpha_d = alpha_d;
     a.log2_keep = (float)std::log2(1.0 - (double)tau);
+    return a;
+}
+
+hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y, float alpha_l,
+                         float alpha_d, float tau, hipStream_t s, const float *rowmask, float g_sigma,
+                         uint64_t seed, int iteration)
+{
+    const GatherArgs a = gather_args(p, y, alpha_l, alpha_d, tau, rowmask, g_sigma, seed, iteration);
     if (channels == 3) {
         switch (mode) {
         case kGatherAdjoint: gather_launch<3, kGatherAdjoint>(a, s); break;
@@ -1484,9 +1553,8 @@ static void update_launch(const UpdateArgs &a, hipStream_t s)
     hipLaunchKernelGGL((update_kernel<C, MODE>), dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
 }
 
-hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
-                         int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s, float *out2, const int32_t *inside)
+static UpdateArgs update_args(const rte_plan *p, int acc, float lambda, int clamp_nonneg, float *out,
+                              float *temperature, int lut_size, int fit_channel, float *out2, const int32_t *inside)
 {
     UpdateArgs a{};
     a.out2 = out2;
@@ -1512,6 +1580,15 @@ hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, flo
     a.n = p->n_nodes;
     a.lambda = lambda;
     a.clamp_nonneg = clamp_nonneg;
+    return a;
+}
+
+hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
+                         int clamp_nonneg, float *out, float *temperature, int lut_size,
+                         int fit_channel, hipStream_t s, float *out2, const int32_t *inside)
+{
+    const UpdateArgs a =
+        update_args(p, acc, lambda, clamp_nonneg, out, temperature, lut_size, fit_channel, out2, inside);
 #define RTE_UPD(M)                                            \
     case M:                                                   \
         if (channels == 3) update_launch<3, M>(a, s);         \
@@ -1597,6 +1674,86 @@ hipError_t launch_err_reduce(const rte_plan *p, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(err_reduce_kernel, dim3(1), dim3(kBlock), 0, s, p->d_err, p->n_tiles, out);
     return hipGetLastError();
+}
+
+// One reconstruction iteration for n plans with open jobs: one launch per
+// phase (render with residual, voxel-owned gather, update) covering every
+// plan's tiles, bricks and key points. The per-plan arguments and the block
+// prefix tables are staged in plans[0]'s batch buffer.
+template <int C, int EPI, int GMODE, int UMODE>
+static hipError_t step_batch(rte_plan *const *plans, int n, bool scat, hipStream_t s, hipEvent_t *marks)
+{
+    std::vector<RenderArgs> ra(n);
+    std::vector<GatherArgs> ga(n);
+    std::vector<UpdateArgs> ua(n);
+    std::vector<int> rp(n + 1, 0), gp(n + 1, 0), up(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const rte_plan *p = plans[i];
+        const rte_recon_params &q = p->job_params;
+        ra[i] = render_args(p, EPI, p->job_frames, C, 0, p->d_y, nullptr, q.use_mask ? p->d_mask : nullptr, nullptr);
+        ga[i] = gather_args(p, p->d_y, q.alpha_l, q.alpha_d, q.tau, nullptr, q.g_sigma, q.seed, p->job_iter);
+        ua[i] = update_args(p, C, q.lambda, q.clamp_nonneg, nullptr, nullptr, 0, 0, nullptr,
+                            q.use_hull ? p->d_inside : nullptr);
+        rp[i + 1] = rp[i] + ra[i].nb8;
+        gp[i + 1] = gp[i] + ga[i].bx * ga[i].by * ga[i].bz;
+        up[i + 1] = up[i] + blocks_for(ua[i].n);
+    }
+    // staging layout: [render args][gather args][update args][3 prefix tables]
+    char *d = static_cast<char *>(plans[0]->d_batch);
+    const size_t o_r = 0, o_g = o_r + sizeof(RenderArgs) * n, o_u = o_g + sizeof(GatherArgs) * n;
+    const size_t o_p = (o_u + sizeof(UpdateArgs) * n + 15) & ~(size_t)15;
+    const size_t np = (size_t)(n + 1) * sizeof(int);
+    if (o_p + 3 * np > plans[0]->batch_bytes) return hipErrorInvalidValue;
+    // the pinned staging buffer is rewritten only after its previous upload ended
+    hipError_t e = hipEventSynchronize(plans[0]->batch_event);
+    if (e != hipSuccess) return e;
+    char *h = static_cast<char *>(plans[0]->h_batch);
+    std::memcpy(h + o_r, ra.data(), sizeof(RenderArgs) * n);
+    std::memcpy(h + o_g, ga.data(), sizeof(GatherArgs) * n);
+    std::memcpy(h + o_u, ua.data(), sizeof(UpdateArgs) * n);
+    std::memcpy(h + o_p, rp.data(), np);
+    std::memcpy(h + o_p + np, gp.data(), np);
+    std::memcpy(h + o_p + 2 * np, up.data(), np);
+    e = hipMemcpyAsync(d, h, o_p + 3 * np, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(plans[0]->batch_event, s);
+    if (e != hipSuccess) return e;
+    const RenderArgs *dra = reinterpret_cast<const RenderArgs *>(d + o_r);
+    const GatherArgs *dga = reinterpret_cast<const GatherArgs *>(d + o_g);
+    const UpdateArgs *dua = reinterpret_cast<const UpdateArgs *>(d + o_u);
+    const int *drp = reinterpret_cast<const int *>(d + o_p), *dgp = reinterpret_cast<const int *>(d + o_p + np),
+              *dup = reinterpret_cast<const int *>(d + o_p + 2 * np);
+    // marks (optional): start/stop events around the render, gather and update launches
+    auto mark = [&](int i) { if (marks && marks[i]) hipEventRecord(marks[i], s); };
+    mark(0);
+    if (rp[n] > 0) {
+        if (scat)
+            hipLaunchKernelGGL((render_batch_kernel<C, true, true, false, EPI>), dim3(rp[n]), dim3(kBlock), 0, s, dra, drp, n);
+        else
+            hipLaunchKernelGGL((render_batch_kernel<C, true, false, false, EPI>), dim3(rp[n]), dim3(kBlock), 0, s, dra, drp, n);
+    }
+    mark(1);
+    mark(2);
+    if (gp[n] > 0) hipLaunchKernelGGL((gather_batch_kernel<C, GMODE>), dim3(gp[n]), dim3(kBlock), 0, s, dga, dgp, n);
+    mark(3);
+    mark(4);
+    if (up[n] > 0) hipLaunchKernelGGL((update_batch_kernel<C, UMODE>), dim3(up[n]), dim3(kBlock), 0, s, dua, dup, n);
+    mark(5);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(rte_plan *const *plans, int n, hipStream_t s, hipEvent_t *marks)
+{
+    const int C = plans[0]->params.channels;
+    const bool scat = plans[0]->params.albedo > 0.0f && plans[0]->params.scatter_res >= 2;
+    const int upd = plans[0]->job_params.update;
+#define RTE_STEP(CC)                                                                                   \
+    if (upd == RTE_UPDATE_SART) return step_batch<CC, kEpiSart, kGatherAdjoint, kUpdSart>(plans, n, scat, s, marks); \
+    if (upd == RTE_UPDATE_MLEM) return step_batch<CC, kEpiMlem, kGatherAdjoint, kUpdMlem>(plans, n, scat, s, marks); \
+    return step_batch<CC, kEpiPaper, kGatherPaper, kUpdPaper>(plans, n, scat, s, marks);
+    if (C == 3) { RTE_STEP(3) }
+    RTE_STEP(1)
+#undef RTE_STEP
 }
 
 }  // namespace rte

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "LIB_PATH", "lib", "RteError", "Plan", "TempParams", "plan_create", "render", "inscatter",
     "backproject", "reconstruct", "reconstruct_temperature", "temperature_map",
-    "temperature_invert", "KERNELS", "UPDATES",
+    "temperature_invert", "KERNELS", "UPDATES", "job_step",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
@@ -119,6 +119,9 @@ def lib():
     L.rte_temperature_map.argtypes = [vp, vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_invert.argtypes = [vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_lut.argtypes = [vp, P(_TempParams), P(ct.c_float), i32]
+    L.rte_job_begin.argtypes = [vp, vp, vp, vp, P(ReconParams), vp]
+    L.rte_job_step.argtypes = [P(vp), i32, vp]
+    L.rte_job_end.argtypes = [vp, vp, vp]
     L.rte_reconstruct_stats.argtypes = [vp, P(ct.c_int32), P(ct.c_int32), P(ct.c_float), i32]
     L.rte_flame_mask.argtypes = [vp, vp, ct.c_float, vp, vp]
     L.rte_visual_hull.argtypes = [vp, vp, vp, vp]
@@ -320,6 +323,28 @@ class Plan:
             ct.byref(temp.c()), _stream()))
         return temperature
 
+    def job_begin(self, frames, extinction, emission=None, update="sart", lam=1.0,
+                  clamp_nonneg=True, flame_threshold=None, hull=False, outside_value=0.0):
+        """Open a job; emission None keeps the volume resident in the plan."""
+        C = self.channels
+        rp = ReconParams(update=UPDATES[update], lam=lam, clamp_nonneg=1 if clamp_nonneg else 0,
+                         alpha_l=1e-3, alpha_d=1.0, tau=0.05,
+                         use_mask=0 if flame_threshold is None else 1,
+                         flame_threshold=0.0 if flame_threshold is None else flame_threshold,
+                         use_hull=1 if hull else 0, outside_value=outside_value)
+        self._job_frames = frames  # keep the caller's frames alive while the job is open
+        _check(lib().rte_job_begin(self._h, _ptr(frames, self.img_shape(), "frames"),
+                                   _ptr(extinction, self.vol_shape, "extinction"),
+                                   _ptr(emission, (C,) + self.vol_shape, "emission"), ct.byref(rp),
+                                   _stream()))
+
+    def job_end(self, emission=None):
+        C = self.channels
+        _check(lib().rte_job_end(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
+                                 _stream()))
+        self._job_frames = None
+        return emission
+
     def stats(self, max_errors=1024):
         """(updates made, per-iteration image RMS) of the last reconstruct()."""
         n, ne = ct.c_int32(), ct.c_int32()
@@ -388,6 +413,12 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def job_step(plans):
+    """One iteration for every plan with an open job, batched in one launch per phase."""
+    arr = (ct.c_void_p * len(plans))(*[p._h for p in plans])
+    _check(lib().rte_job_step(arr, len(plans), _stream()))
 
 
 # Functional aliases with the ABI's names.

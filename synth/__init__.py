@@ -244,3 +244,84 @@ CONFIGS = {
     "temperature": dict(n=128, views=8, width=512, height=512, fov=40.0, radius=3.0,
                         step_vox=0.5, channels=1, albedo=0.0, iters=30),
 }
+
+
+# ----------------------------------------------------------------- videos
+@dataclasses.dataclass
+class VideoSpec:
+    """One synthetic flame video: a grid, a camera rig and plume blobs whose
+    centres drift with a seeded per-blob velocity (frame-to-frame advection)."""
+
+    video: int
+    grid: Grid
+    rig: Rig
+    centres: np.ndarray   # [B, 3] at frame 0
+    velocity: np.ndarray  # [B, 3] per frame
+    covs: list
+    peaks: np.ndarray     # [B, 4]: RGB emission, extinction
+
+    def centres_at(self, frame: int) -> np.ndarray:
+        c = self.centres + frame * self.velocity
+        # keep the plumes inside the box: reflect at the [0.2, 0.8] walls
+        c = np.abs(((c - 0.2) % 1.2) - 0.6) + 0.2
+        return c
+
+
+SERVE_GRIDS = (64, 128, 192, 256)
+SERVE_IMAGES = ((256, 256), (512, 512), (640, 480), (1024, 768))
+
+
+def video_spec(video: int, seed: int = 0, n_blobs: int = 12) -> VideoSpec:
+    """Grid size from {64,128,192,256}^3, 4-12 ring views, image size from
+    {256^2, 512^2, 640x480, 1024x768}, all drawn from the seed."""
+    rng = np.random.default_rng([seed, video])
+    n = int(rng.choice(SERVE_GRIDS))
+    views = int(rng.integers(4, 13))
+    W, H = SERVE_IMAGES[int(rng.integers(0, len(SERVE_IMAGES)))]
+    centres, covs = _plume_blobs(rng, n_blobs)
+    rgb = np.array([[1.0, rng.uniform(0.4, 0.8), rng.uniform(0.1, 0.3)] for _ in range(n_blobs)])
+    rgb *= rng.uniform(0.5, 1.0, size=(n_blobs, 1))
+    sig = rng.uniform(0.5, 4.0, size=(n_blobs, 1))
+    vel = rng.normal(scale=0.004, size=(n_blobs, 3)) + np.array([0.0, 0.0, 0.003])
+    rig = ring_rig(views, W, H, elevation_jitter_deg=10.0, seed=seed * 1000 + video)
+    return VideoSpec(video, Grid(n, n, n), rig, np.array(centres), vel, covs,
+                     np.concatenate([rgb, sig], axis=1))
+
+
+def blob_fields_torch(grid: Grid, centres, covs, peaks, device="cuda"):
+    """blob_fields evaluated with torch on `device` (float64 arithmetic, float32
+    result) for large grids."""
+    import torch
+    xs = torch.linspace(grid.lo[0], grid.hi[0], grid.nx, dtype=torch.float64, device=device)
+    ys = torch.linspace(grid.lo[1], grid.hi[1], grid.ny, dtype=torch.float64, device=device)
+    zs = torch.linspace(grid.lo[2], grid.hi[2], grid.nz, dtype=torch.float64, device=device)
+    peaks = np.asarray(peaks, float).reshape(len(centres), -1)
+    out = torch.zeros((peaks.shape[1],) + grid.shape_zyx, dtype=torch.float64, device=device)
+    for c, cov, pk in zip(centres, covs, peaks):
+        A = np.linalg.inv(np.asarray(cov, float))
+        dx = (xs - c[0])[None, None, :]
+        dy = (ys - c[1])[None, :, None]
+        dz = (zs - c[2])[:, None, None]
+        q = (A[0, 0] * dx * dx + A[1, 1] * dy * dy + A[2, 2] * dz * dz
+             + 2.0 * A[0, 1] * dx * dy + 2.0 * A[0, 2] * dx * dz + 2.0 * A[1, 2] * dy * dz)
+        gb = torch.exp(-0.5 * q)
+        for f in range(peaks.shape[1]):
+            out[f] += float(pk[f]) * gb
+    return out.float()
+
+
+def video_frame(spec: VideoSpec, frame: int, device=None):
+    """(emission [3,n,n,n], extinction [n,n,n]) of one frame: numpy when device
+    is None, else torch tensors on that device."""
+    c = spec.centres_at(frame)
+    if device is None:
+        f = blob_fields(spec.grid, c, spec.covs, spec.peaks)
+        return f[:3].copy(), f[3].copy()
+    f = blob_fields_torch(spec.grid, c, spec.covs, spec.peaks, device)
+    return f[:3].contiguous(), f[3].contiguous()
+
+
+def poisson_arrivals(n_jobs: int, rate: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n_jobs))

@@ -1,0 +1,211 @@
+"""Serving: the job API (rte_job_begin / rte_job_step / rte_job_end) and the
+continuous-batching loop. Batched steps must give every job bitwise the result
+it gets alone, the job path must equal rte_reconstruct, and at a small size
+both agree with the FP64 oracle's reconstruction."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import VOLUME_RMS, as64, dev, f32, host, rel_rms, say
+
+pytestmark = pytest.mark.gpu
+
+
+def rte():
+    from paper_1809_06417_amd import rte as _rte
+    return _rte
+
+
+def small_spec(video, n, views, W, H):
+    """A seeded video spec with its grid and rig shrunk to oracle-friendly sizes."""
+    spec = synth.video_spec(video, seed=5)
+    return dataclasses.replace(spec, grid=synth.Grid(n, n, n),
+                               rig=synth.ring_rig(views, W, H, elevation_jitter_deg=10.0, seed=50 + video))
+
+
+SMALL = [small_spec(0, 20, 3, 40, 32), small_spec(1, 24, 4, 36, 36), small_spec(2, 17, 2, 48, 30)]
+
+
+def frame_inputs(spec, frame):
+    """(frames, extinction) of one frame; frames are FP64 oracle renders of the
+    ground truth at that frame, rounded to FP32."""
+    em, sig = synth.video_frame(spec, frame)
+    em, sig = f32(em), f32(sig)
+    F = oracle.render(spec.grid, spec.rig, as64(em), as64(sig), step_vox=0.5)
+    return f32(F), sig
+
+
+def new_plan(spec):
+    return rte().Plan(spec.grid, spec.rig, channels=3, step_vox=0.5)
+
+
+@pytest.mark.parametrize("update", ["sart", "mlem", "paper"])
+def test_job_path_equals_reconstruct(update):
+    import torch
+    spec = SMALL[0]
+    F, sig = frame_inputs(spec, 0)
+    say("job vs reconstruct", update)
+    with new_plan(spec) as p:
+        start = dev(np.full((3,) + spec.grid.shape_zyx, 0.05))
+        a = start.clone()
+        p.reconstruct(dev(F), dev(sig), a, 4, update=update)
+        b = torch.empty_like(start)
+        p.job_begin(dev(F), dev(sig), start, update=update)
+        for _ in range(4):
+            rte().job_step([p])
+        p.job_end(b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert p.stats()[0] == 4
+
+
+def test_batched_steps_match_each_job_alone():
+    """Three plans of different grids, view counts and image sizes advance
+    together; each result is bitwise its result alone."""
+    import torch
+    say("batched vs alone")
+    plans = [new_plan(s) for s in SMALL]
+    try:
+        inputs = [frame_inputs(s, 3) for s in SMALL]
+        alone = []
+        for p, (F, sig) in zip(plans, inputs):
+            out = torch.zeros((3,) + p.vol_shape, device="cuda")
+            p.reconstruct(dev(F), dev(sig), out, 5)
+            alone.append(out)
+        held = [(dev(F), dev(sig)) for F, sig in inputs]
+        for p, (Fd, sd) in zip(plans, held):
+            p.job_begin(Fd, sd, torch.zeros((3,) + p.vol_shape, device="cuda"))
+        # a ragged mix: plan 2 joins one step late and leaves one step late
+        rte().job_step(plans[:2])
+        rte().job_step(plans)
+        rte().job_step(plans[1:])
+        rte().job_step([plans[2], plans[0]])
+        rte().job_step(plans)
+        rte().job_step([plans[1], plans[0]])
+        mixed = []
+        for p in plans:
+            out = torch.empty((3,) + p.vol_shape, device="cuda")
+            p.job_end(out)
+            mixed.append(out)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(alone, mixed)):
+            assert torch.equal(a, b), i
+    finally:
+        for p in plans:
+            p.close()
+
+
+def test_warm_start_keeps_the_resident_volume():
+    import torch
+    spec = SMALL[1]
+    (F0, s0), (F1, s1) = frame_inputs(spec, 0), frame_inputs(spec, 1)
+    say("warm start")
+    with new_plan(spec) as p:
+        ref = torch.zeros((3,) + p.vol_shape, device="cuda")
+        p.reconstruct(dev(F0), dev(s0), ref, 3)
+        p.reconstruct(dev(F1), dev(s1), ref, 3)
+        f0, f1 = dev(F0), dev(F1)
+        p.job_begin(f0, dev(s0), torch.zeros_like(ref))
+        for _ in range(3):
+            rte().job_step([p])
+        p.job_end(None)
+        p.job_begin(f1, dev(s1), None)  # start from the resident result
+        for _ in range(3):
+            rte().job_step([p])
+        out = torch.empty_like(ref)
+        p.job_end(out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+
+
+def test_job_path_matches_oracle():
+    spec = SMALL[2]
+    F, sig = frame_inputs(spec, 2)
+    em0 = np.zeros((3,) + spec.grid.shape_zyx)
+    ref = oracle.reconstruct(spec.grid, spec.rig, as64(F), as64(sig), em0, 6)
+    say("job vs oracle")
+    import torch
+    with new_plan(spec) as p:
+        out = torch.empty((3,) + p.vol_shape, device="cuda")
+        p.job_begin(dev(F), dev(sig), dev(em0))
+        for _ in range(6):
+            rte().job_step([p])
+        p.job_end(out)
+        got = host(out)
+    assert rel_rms(got, ref) <= VOLUME_RMS
+
+
+def test_job_api_rejects_bad_batches():
+    import torch
+    say("job errors")
+    a, b = new_plan(SMALL[0]), rte().Plan(SMALL[1].grid, SMALL[1].rig, channels=1)
+    try:
+        F, sig = frame_inputs(SMALL[0], 0)
+        with pytest.raises(rte().RteError):
+            rte().job_step([a])                       # no open job
+        Fd = dev(F)
+        a.job_begin(Fd, dev(sig), torch.zeros((3,) + a.vol_shape, device="cuda"))
+        with pytest.raises(rte().RteError):
+            a.job_begin(Fd, dev(sig), None)           # already open
+        with pytest.raises(rte().RteError):
+            rte().job_step([a, a])                    # listed twice
+        F1 = torch.zeros((SMALL[1].rig.n_views, 1, SMALL[1].rig.height, SMALL[1].rig.width), device="cuda")
+        b.job_begin(F1, torch.zeros(b.vol_shape, device="cuda"), torch.zeros((1,) + b.vol_shape, device="cuda"))
+        with pytest.raises(rte().RteError):
+            rte().job_step([a, b])                    # mixed channel counts
+        before = torch.zeros((3,) + a.vol_shape, device="cuda")
+        a.job_end(before)
+        b.job_end(None)
+        torch.cuda.synchronize()
+        assert a.stats()[0] == 0                      # the rejected steps advanced nothing
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("budget", ["ample", "one_plan"])
+def test_serving_loop_matches_sequential(budget):
+    """The continuous-batching loop (with LRU eviction of idle plans when the
+    HBM budget holds only one plan) returns, per job, bitwise the volume of
+    the one-job-at-a-time reference in arrival order."""
+    import torch
+    from paper_1809_06417_amd import serve
+    arrivals = synth.poisson_arrivals(12, 400.0, seed=2)
+    vids = np.random.default_rng(4).integers(0, len(SMALL), size=len(arrivals))
+    say("serving loop", budget)
+
+    def make_jobs():
+        count = {}
+        jobs = []
+        for i, (t, v) in enumerate(zip(arrivals, vids)):
+            fr = count.get(int(v), 0)
+            count[int(v)] = fr + 1
+            F, sig = inputs[(int(v), fr)]
+            jobs.append(serve.Job(i, int(v), fr, float(t), dev(F), dev(sig)))
+        return jobs
+
+    count = {}
+    inputs = {}
+    for v in vids:
+        fr = count.get(int(v), 0)
+        count[int(v)] = fr + 1
+        inputs[(int(v), fr)] = frame_inputs(SMALL[int(v)], fr)
+
+    videos = {i: serve.VideoState(s) for i, s in enumerate(SMALL)}
+    cap = max(v.plan_bytes for v in videos.values()) + 1 if budget == "one_plan" else 1 << 34
+    jobs = serve.serve(videos, make_jobs(), iters=4, hbm_budget_bytes=cap, keep_results=True)
+    for v in videos.values():
+        v.evict()
+    ref_videos = {i: serve.VideoState(s) for i, s in enumerate(SMALL)}
+    ref = serve.serve_sequential(ref_videos, make_jobs(), iters=4, keep_results=True)
+    for v in ref_videos.values():
+        v.evict()
+    torch.cuda.synchronize()
+    for a, b in zip(sorted(jobs, key=lambda j: j.jid), sorted(ref, key=lambda j: j.jid)):
+        assert a.done is not None and a.done >= a.arrival
+        assert torch.equal(a.result, b.result), a.jid
+    s = serve.latency_summary(jobs)
+    assert s["jobs"] == 12 and s["p99_ms"] >= s["p50_ms"] > 0

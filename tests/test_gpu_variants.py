@@ -78,14 +78,14 @@ def test_masked_hull_reconstruction_matches_oracle(update):
 
 def test_paper_gains_match_oracle():
     g, rig, em, sig, F, thr = flame_case()
-    kw = dict(step_vox=STEP, mode="paper", g_sigma=0.3, seed=123456789012345)
+    kw = dict(step_vox=STEP, mode="paper", g_sigma=1.0, seed=123456789012345)
     ref, _, _ = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), np.zeros(em.shape), 3, **kw)
     plain = oracle.reconstruct(g, rig, as64(F), as64(sig), np.zeros(em.shape), 3, step_vox=STEP, mode="paper")
     say("paper gains")
     with rte().Plan(g, rig, channels=1, step_vox=STEP) as p:
-        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 3, update="paper", g_sigma=0.3,
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 3, update="paper", g_sigma=1.0,
                                seed=123456789012345))
-    assert rel_rms(ref, plain) > 10 * VOLUME_RMS  # the gains matter
+    assert rel_rms(ref, plain) > 5 * VOLUME_RMS  # the gains matter
     assert rel_rms(x, ref) <= VOLUME_RMS
 
 
