@@ -11,13 +11,25 @@ module marshals numpy arrays into it with ctypes.
 Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``):
   ray_table            pinned (chord closed forms, symmetry, point projection)
   render               pinned (Beer-Lambert, sigma = 0 affine line integral,
-                       fine-quadrature limit, 90-degree symmetry, point projection)
+                       fine-quadrature limit, 90-degree symmetry, point projection,
+                       per-view in-scatter grids in a constant medium)
   inscatter            pinned (closed form for constant fields, sigma = 0 limit)
+  inscatter (phase_g)  pinned (g = 0 reduces to the isotropic grid, sigma = 0
+                       closed form, forward/backward brightening, |g| -> 1 limit)
   backproject_adjoint  pinned (adjoint identity, dense-matrix transpose)
   backproject_paper    pinned (hand-computed single-ray worked case)
-  reconstruct          pinned (dense least-squares recovery, SIRT monotone residual)
+  reconstruct          pinned (dense least-squares recovery, SIRT monotone residual,
+                       EM step = dense formula with likelihood ascent, fixed point
+                       with the phase function)
+  render_grad          pinned (central differences of render, adjoint identity)
+  philox4x32_10        pinned (uniformity, word independence, avalanche)
+  sample_gain          pinned (mean one, requested spread)
+  flame_mask / hull    pinned (threshold definition, hull contains the flame and
+                       shrinks as views are added)
+  reconstruct_ext      pinned (reduces to reconstruct, masked and hull properties,
+                       stop rule)
   planck / band / lut  pinned (Stefan-Boltzmann integral, Wien peak, LUT vs
                        direct integral within the interpolation bound)
-  temperature_fit      pinned (fixed point at the true temperature)
+  temperature_fit      pinned (fixed point at the true temperature, residual descent)
 """
 from .oracle import *  # noqa: F401,F403

@@ -59,14 +59,15 @@ def lib():
         d, i32 = ct.c_double, ct.c_int32
         dp = P(ct.c_double)
         _lib.orc_ray_table.argtypes = [P(_Grid), P(_Camera), i32, d, dp, dp, P(ct.c_int32)]
-        _lib.orc_render.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, dp, dp, i32, dp, dp, dp]
+        _lib.orc_render.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, dp, dp, i32, dp, i32, dp, dp]
         _lib.orc_inscatter.argtypes = [P(_Grid), i32, dp, dp, i32, i32, d, dp]
+        _lib.orc_inscatter_phase.argtypes = [P(_Grid), P(_Camera), i32, i32, dp, dp, i32, i32, d, d, dp]
         _lib.orc_backproject_adjoint.argtypes = [P(_Grid), P(_Camera), i32, i32, d, dp, dp, dp]
         _lib.orc_backproject_paper.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, d, dp, dp]
-        _lib.orc_reconstruct.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d, dp,
+        _lib.orc_reconstruct.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d, d, dp,
                                          dp, dp, i32, i32, d, i32, d, d, d, dp]
         _lib.orc_render_grad.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, dp, dp, i32, dp,
-                                         dp, dp, dp]
+                                         i32, dp, dp, dp]
         u32p = P(ct.c_uint32)
         _lib.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         _lib.orc_philox4x32_10.restype = None
@@ -75,7 +76,7 @@ def lib():
         _lib.orc_flame_mask.argtypes = [dp, i32, i32, ct.c_long, d, dp]
         _lib.orc_flame_mask.restype = None
         _lib.orc_visual_hull.argtypes = [P(_Grid), P(_Camera), i32, d, dp, P(ct.c_int32)]
-        _lib.orc_reconstruct_ext.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d,
+        _lib.orc_reconstruct_ext.argtypes = [P(_Grid), P(_Camera), i32, i32, d, d, d, i32, i32, d, d,
                                              dp, dp, dp, i32, P(_ReconParams), dp, P(ct.c_int32)]
         _lib.orc_planck.argtypes = [d, d]
         _lib.orc_planck.restype = d
@@ -139,9 +140,19 @@ def ray_table(grid, rig, step_vox=0.5):
     return tn, tf, K
 
 
+def _scatter_views(S, V):
+    """0 for one in-scatter grid [C, M, M, M], 1 for one per view [V, C, M, M, M]."""
+    if S is None or S.ndim == 4:
+        return 0
+    if S.ndim != 5 or S.shape[0] != V:
+        raise ValueError(f"in-scatter grids of shape {S.shape} do not match {V} views")
+    return 1
+
+
 def render(grid, rig, emission, extinction, *, step_vox=0.5, albedo=0.0, background=0.0,
            inscatter=None, rowsum=False):
-    """Images [V, C, H, W] (and row sums [V, H, W] when rowsum=True)."""
+    """Images [V, C, H, W] (and row sums [V, H, W] when rowsum=True).
+    inscatter: [C, M, M, M] (isotropic) or [V, C, M, M, M] (one grid per view)."""
     em = _f64(emission)
     C = em.shape[0]
     sig = _f64(extinction)
@@ -152,7 +163,7 @@ def render(grid, rig, emission, extinction, *, step_vox=0.5, albedo=0.0, backgro
     s_res = 0 if S is None else S.shape[-1]
     _check(lib().orc_render(ct.byref(_grid(grid)), _cams(rig), V, C, float(step_vox),
                             float(albedo), float(background), _dp(em), _dp(sig), s_res,
-                            _dp(S) if S is not None else None, _dp(img),
+                            _dp(S) if S is not None else None, _scatter_views(S, V), _dp(img),
                             _dp(rs) if rs is not None else None), "render")
     return (img, rs) if rowsum else img
 
@@ -170,13 +181,26 @@ def render_grad(grid, rig, emission, extinction, dLdI, *, step_vox=0.5, albedo=0
     _check(lib().orc_render_grad(ct.byref(_grid(grid)), _cams(rig), rig.n_views, C,
                                  float(step_vox), float(albedo), float(background), _dp(em),
                                  _dp(_f64(extinction)), s_res, _dp(S) if S is not None else None,
-                                 _dp(_f64(dLdI)), _dp(d_em), _dp(d_sig)), "render_grad")
+                                 _scatter_views(S, rig.n_views), _dp(_f64(dLdI)), _dp(d_em),
+                                 _dp(d_sig)), "render_grad")
     return d_em, d_sig
 
 
-def inscatter(grid, emission, extinction, *, s_res=32, n_dirs=32, s_step=0.5):
+def inscatter(grid, emission, extinction, *, s_res=32, n_dirs=32, s_step=0.5, phase_g=0.0, rig=None,
+              per_view=False):
+    """In-scatter grid [C, M, M, M] (phase_g = 0), or one grid per view of
+    `rig` [V, C, M, M, M] for the Henyey-Greenstein phase function (phase_g != 0,
+    or per_view=True)."""
     em = _f64(emission)
     C = em.shape[0]
+    if phase_g != 0.0 or per_view:
+        if rig is None:
+            raise ValueError("an anisotropic phase function needs the camera rig")
+        S = np.zeros((rig.n_views, C, s_res, s_res, s_res))
+        _check(lib().orc_inscatter_phase(ct.byref(_grid(grid)), _cams(rig), rig.n_views, C, _dp(em),
+                                         _dp(_f64(extinction)), s_res, n_dirs, float(s_step),
+                                         float(phase_g), _dp(S)), "inscatter_phase")
+        return S
     S = np.zeros((C, s_res, s_res, s_res))
     _check(lib().orc_inscatter(ct.byref(_grid(grid)), C, _dp(em), _dp(_f64(extinction)), s_res,
                                n_dirs, float(s_step), _dp(S)), "inscatter")
@@ -204,7 +228,7 @@ def backproject_paper(grid, rig, residual, *, step_vox=0.5, alpha_l=1e-3, alpha_
 
 
 def reconstruct(grid, rig, frames, extinction, emission0, iters, *, step_vox=0.5, albedo=0.0,
-                background=0.0, s_res=32, n_dirs=32, s_step=0.5, mode="sart", lam=1.0,
+                background=0.0, s_res=32, n_dirs=32, s_step=0.5, phase_g=0.0, mode="sart", lam=1.0,
                 clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, return_residuals=False):
     F = _f64(frames)
     em = np.array(emission0, dtype=np.float64, order="C", copy=True)
@@ -212,7 +236,7 @@ def reconstruct(grid, rig, frames, extinction, emission0, iters, *, step_vox=0.5
     res = np.zeros(max(iters, 1))
     _check(lib().orc_reconstruct(ct.byref(_grid(grid)), _cams(rig), rig.n_views, C,
                                  float(step_vox), float(albedo), float(background), int(s_res),
-                                 int(n_dirs), float(s_step), _dp(F), _dp(_f64(extinction)),
+                                 int(n_dirs), float(s_step), float(phase_g), _dp(F), _dp(_f64(extinction)),
                                  _dp(em), int(iters), {"sart": 0, "paper": 1, "mlem": 2}[mode], float(lam),
                                  1 if clamp_nonneg else 0, float(alpha_l), float(alpha_d),
                                  float(tau), _dp(res)), "reconstruct")
@@ -314,7 +338,7 @@ def visual_hull(grid, rig, mask, *, step_vox=0.5):
 
 
 def reconstruct_ext(grid, rig, frames, extinction, emission0, iters, *, step_vox=0.5, albedo=0.0,
-                    background=0.0, s_res=32, n_dirs=32, s_step=0.5, mode="sart", lam=1.0,
+                    background=0.0, s_res=32, n_dirs=32, s_step=0.5, phase_g=0.0, mode="sart", lam=1.0,
                     clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, g_sigma=0.0, seed=0,
                     flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0):
     """Reconstruction with the paper's variants (flame mask, visual hull, gains
@@ -333,7 +357,8 @@ def reconstruct_ext(grid, rig, frames, extinction, emission0, iters, *, step_vox
     done = ct.c_int32()
     _check(lib().orc_reconstruct_ext(ct.byref(_grid(grid)), _cams(rig), rig.n_views, em.shape[0],
                                      float(step_vox), float(albedo), float(background), int(s_res),
-                                     int(n_dirs), float(s_step), _dp(F), _dp(_f64(extinction)),
-                                     _dp(em), int(iters), ct.byref(rp), _dp(res), ct.byref(done)),
+                                     int(n_dirs), float(s_step), float(phase_g), _dp(F),
+                                     _dp(_f64(extinction)), _dp(em), int(iters), ct.byref(rp), _dp(res),
+                                     ct.byref(done)),
            "reconstruct_ext")
     return em, res[:iters], int(done.value)

@@ -261,9 +261,21 @@ int orc_ray_table(const orc_grid *g, const orc_camera *cams, int32_t V, double s
  *
  * em [C][N], sig [N], S [C][s_res^3] or NULL, img [V][C][H][W].
  * rowsum [V][H][W] (optional) receives sum_k T_k Delta_k phi_k. */
+/* In-scatter grid seen by view v: one grid [C][M^3] shared by all views
+ * (isotropic phase function), or grids [V][C][M^3], one per view
+ * (anisotropic phase function, see orc_inscatter_phase). */
+static const double *view_grid(const double *S, int s_views, int v, int C, int s_res)
+{
+    return s_views ? S + (long)v * C * s_res * s_res * s_res : S;
+}
+
+/* Render every view (Eq. 5-8 with the segment rule above). img [V][C][H][W];
+ * rowsum (optional) [V][H][W] receives sum_k T_k Delta_k phi_k, the row sums
+ * of the linear emission -> image map. S: in-scatter grid(s) as described at
+ * view_grid, NULL without in-scattering. */
 int orc_render(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
                double albedo, double background, const double *em, const double *sig,
-               int32_t s_res, const double *S, double *img, double *rowsum)
+               int32_t s_res, const double *S, int32_t s_views, double *img, double *rowsum)
 {
     if (C < 1) return -1;
     double ds = step_vox * grid_min_spacing(g);
@@ -276,6 +288,7 @@ int orc_render(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, 
         const orc_camera *c = &cams[v];
         if (!camera_index_ok(c)) return -1;
         long HW = (long)c->width * c->height;
+        const double *Sv = S ? view_grid(S, s_views, v, C, s_res) : NULL;
 #pragma omp parallel for schedule(static)
         for (long p = 0; p < HW; ++p) {
             int u = (int)(p % c->width), vv = (int)(p / c->width);
@@ -299,7 +312,7 @@ int orc_render(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, 
                         if (S && albedo != 0.0) {
                             double qs[3];
                             to_grid_coords(&sg, x, qs);
-                            j += albedo * s * trilerp(&sg, S + (long)ch * s_res * s_res * s_res, qs);
+                            j += albedo * s * trilerp(&sg, Sv + (long)ch * s_res * s_res * s_res, qs);
                         }
                         I[ch] += wgt * j;
                     }
@@ -374,6 +387,96 @@ int orc_inscatter(const orc_grid *g, int32_t C, const double *em, const double *
         }
         for (int ch = 0; ch < C; ++ch) S[(long)ch * M3 + m] = acc[ch] / (double)n_dirs;
     }
+    return 0;
+}
+
+/* Henyey-Greenstein phase function in the form of Eq. 9, p(w, w_i) with
+ * w the direction of interest (the direction the scattered light travels)
+ * and w_i the direction the incident light comes from (pointing from the
+ * point towards its source). With the plus sign of Eq. 9, g > 0 peaks at
+ * w = -w_i: light keeps travelling the way it went (forward scattering). */
+static double hg_phase(double g, double w_dot_wi)
+{
+    return (1.0 - g * g) / (4.0 * M_PI * pow(1.0 + g * g + 2.0 * g * w_dot_wi, 1.5));
+}
+
+/* In-scattered radiance for an anisotropic phase function (Eq. 5 third term
+ * with Eq. 9, g != 0). The scattered radiance depends on the direction of
+ * interest, which for a pinhole view v at a point p is fixed by p itself:
+ * the light travels from p to the camera centre o_v, w = (o_v - p)/|o_v - p|.
+ * So each view sees its own grid over the same nodes:
+ *   S_vc(p) = sum_d W_d L_c(p <- u_d) / sum_d W_d,  W_d = p(w, u_d),
+ * with L_c(p <- u_d) the same emission-absorption march as orc_inscatter
+ * (light arriving from u_d) and the phase weights normalised over the
+ * directions, so that a radiance field equal in every direction scatters
+ * into itself (the discrete phase function integrates to one). At g = 0
+ * this is orc_inscatter for every view. A node at a camera centre has no
+ * direction of interest and takes the mean (g = 0).
+ * S [V][C][M^3]. */
+int orc_inscatter_phase(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, const double *em,
+                        const double *sig, int32_t s_res, int32_t n_dirs, double s_step, double phase_g,
+                        double *S)
+{
+    if (s_res < 2 || n_dirs < 1 || n_dirs > 256 || C > 16 || !(fabs(phase_g) < 1.0)) return -1;
+    long N = grid_nodes(g);
+    orc_grid sg;
+    for (int a = 0; a < 3; ++a) { sg.n[a] = s_res; sg.lo[a] = g->lo[a]; sg.hi[a] = g->hi[a]; }
+    double hs[3];
+    grid_spacing(&sg, hs);
+    double ds = s_step * grid_min_spacing(&sg);
+    long M3 = (long)s_res * s_res * s_res;
+    /* camera centres o = -R^T t */
+    double *centre = (double *)malloc(sizeof(double) * 3 * V);
+    if (!centre) return -2;
+    for (int v = 0; v < V; ++v)
+        for (int a = 0; a < 3; ++a)
+            centre[3 * v + a] = -(cams[v].R[0 * 3 + a] * cams[v].t[0] + cams[v].R[1 * 3 + a] * cams[v].t[1] +
+                                  cams[v].R[2 * 3 + a] * cams[v].t[2]);
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < M3; ++m) {
+        int mx = (int)(m % s_res), my = (int)((m / s_res) % s_res), mz = (int)(m / ((long)s_res * s_res));
+        double p[3] = {g->lo[0] + mx * hs[0], g->lo[1] + my * hs[1], g->lo[2] + mz * hs[2]};
+        double L[256][16];
+        double U[256][3];
+        for (int dd = 0; dd < n_dirs; ++dd) {
+            double tn, tf;
+            fib_dir(dd, n_dirs, U[dd]);
+            for (int ch = 0; ch < C; ++ch) L[dd][ch] = 0.0;
+            if (!ray_box(g->lo, g->hi, p, U[dd], &tn, &tf)) continue;
+            int K = n_segments(tn, tf, ds);
+            double T = 1.0;
+            for (int k = 0; k < K; ++k) {
+                double t, len, x[3], q[3];
+                segment(tn, tf, ds, k, &t, &len);
+                for (int a = 0; a < 3; ++a) x[a] = p[a] + t * U[dd][a];
+                to_grid_coords(g, x, q);
+                double s = trilerp(g, sig, q);
+                if (s < 0.0) s = 0.0;
+                double wgt = T * len * phi(s * len);
+                for (int ch = 0; ch < C; ++ch) L[dd][ch] += wgt * trilerp(g, em + (long)ch * N, q);
+                T *= exp(-s * len);
+            }
+        }
+        for (int v = 0; v < V; ++v) {
+            double w[3], nrm = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                w[a] = centre[3 * v + a] - p[a];
+                nrm += w[a] * w[a];
+            }
+            nrm = sqrt(nrm);
+            double num[16], den = 0.0;
+            for (int ch = 0; ch < C; ++ch) num[ch] = 0.0;
+            for (int dd = 0; dd < n_dirs; ++dd) {
+                double W = 1.0;
+                if (nrm > 0.0)
+                    W = hg_phase(phase_g, (w[0] * U[dd][0] + w[1] * U[dd][1] + w[2] * U[dd][2]) / nrm);
+                den += W;
+                for (int ch = 0; ch < C; ++ch) num[ch] += W * L[dd][ch];
+            }
+            for (int ch = 0; ch < C; ++ch) S[((long)v * C + ch) * M3 + m] = num[ch] / den;
+        }
+    }
+    free(centre);
     return 0;
 }
 
@@ -526,7 +629,8 @@ static double dphi(double x)
  * thread reduced in thread order. */
 int orc_render_grad(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
                     double albedo, double background, const double *em, const double *sig,
-                    int32_t s_res, const double *S, const double *dLdI, double *d_em, double *d_sig)
+                    int32_t s_res, const double *S, int32_t s_views, const double *dLdI, double *d_em,
+                    double *d_sig)
 {
     double ds = step_vox * grid_min_spacing(g);
     long N = grid_nodes(g);
@@ -540,6 +644,7 @@ int orc_render_grad(const orc_grid *g, const orc_camera *cams, int32_t V, int32_
     for (int v = 0; v < V; ++v) {
         const orc_camera *c = &cams[v];
         long HW = (long)c->width * c->height;
+        const double *Sv = S ? view_grid(S, s_views, v, C, s_res) : NULL;
 #pragma omp parallel num_threads(nt)
         {
             double *acc = priv + (long)thread_id() * (C + 1) * N;
@@ -577,7 +682,7 @@ int orc_render_grad(const orc_grid *g, const orc_camera *cams, int32_t V, int32_
                         if (S && albedo != 0.0) {
                             double qs[3];
                             to_grid_coords(&sg, x, qs);
-                            Sk[k * C + ch] = trilerp(&sg, S + (long)ch * s_res * s_res * s_res, qs);
+                            Sk[k * C + ch] = trilerp(&sg, Sv + (long)ch * s_res * s_res * s_res, qs);
                         }
                         j[k * C + ch] = trilerp(g, em + (long)ch * N, &q[3 * k]) + albedo * sg_k[k] * Sk[k * C + ch];
                     }
@@ -630,7 +735,8 @@ static long images_size(const orc_camera *cams, int V, int C)
  * given volume, render, compare with the frames, adjust, repeat; Alg. 2).
  * R = A 1 (row sums) and Cs = A^T 1 (column sums) of the linear emission ->
  * image map A at the fixed extinction; rows and columns with zero sum are
- * skipped. I(e) is the full render including in-scattering, whose grid S is
+ * skipped. I(e) is the full render including in-scattering, whose grid S (one
+ * per view when phase_g != 0, orc_inscatter_phase) is
  * recomputed from the current volume at the start of every iteration and
  * held fixed within it.
  *
@@ -645,7 +751,7 @@ static long images_size(const orc_camera *cams, int V, int C)
  * resid_out (optional, [iters]) receives sum (F - I)^2 before each update. */
 int orc_reconstruct(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C,
                     double step_vox, double albedo, double background, int32_t s_res,
-                    int32_t n_dirs, double s_step, const double *frames, const double *sig,
+                    int32_t n_dirs, double s_step, double phase_g, const double *frames, const double *sig,
                     double *em_io, int32_t iters, int32_t mode, double lambda,
                     int32_t clamp_nonneg, double alpha_l, double alpha_d, double tau,
                     double *resid_out)
@@ -663,7 +769,8 @@ int orc_reconstruct(const orc_grid *g, const orc_camera *cams, int32_t V, int32_
     double *ones_n = (double *)malloc(sizeof(double) * N);
     double *ones_img = (double *)malloc(sizeof(double) * V * HW);
     long M3 = (long)s_res * s_res * s_res;
-    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * C * M3) : NULL;
+    long n_grids = phase_g != 0.0 ? V : 1;
+    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * n_grids * C * M3) : NULL;
     int rc = 0;
     if (!img || !y || !delta || !rows || !cols || !ones_n || !ones_img ||
         (albedo != 0.0 && s_res >= 2 && !S)) { rc = -2; goto done; }
@@ -672,17 +779,19 @@ int orc_reconstruct(const orc_grid *g, const orc_camera *cams, int32_t V, int32_
         /* R = A 1 and Cs = A^T 1 for the fixed extinction. */
         for (long i = 0; i < N; ++i) ones_n[i] = 1.0;
         for (long i = 0; i < V * HW; ++i) ones_img[i] = 1.0;
-        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, rows, NULL);
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, 0, rows, NULL);
         if (rc) goto done;
         rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, ones_img, cols);
         if (rc) goto done;
     }
     for (int it = 0; it < iters; ++it) {
         if (S) {
-            rc = orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
+            rc = phase_g != 0.0
+                     ? orc_inscatter_phase(g, cams, V, C, em_io, sig, s_res, n_dirs, s_step, phase_g, S)
+                     : orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
             if (rc) goto done;
         }
-        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, img, NULL);
+        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, phase_g != 0.0, img, NULL);
         if (rc) goto done;
         double r2 = 0.0;
         for (long i = 0; i < NI; ++i) {
@@ -898,7 +1007,7 @@ static int backproject_paper_ext(const orc_grid *g, const orc_camera *cams, int3
  * iters_done receives the number of updates made; resid_out[it] = E_it. */
 int orc_reconstruct_ext(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
                         double albedo, double background, int32_t s_res, int32_t n_dirs, double s_step,
-                        const double *frames, const double *sig, double *em_io, int32_t iters,
+                        double phase_g, const double *frames, const double *sig, double *em_io, int32_t iters,
                         const orc_recon_params *rp, double *resid_out, int32_t *iters_done)
 {
     long N = grid_nodes(g);
@@ -913,7 +1022,8 @@ int orc_reconstruct_ext(const orc_grid *g, const orc_camera *cams, int32_t V, in
     double *mask = (double *)malloc(sizeof(double) * V * HW);
     int32_t *inside = (int32_t *)malloc(sizeof(int32_t) * N);
     long M3 = (long)s_res * s_res * s_res;
-    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * C * M3) : NULL;
+    long n_grids = phase_g != 0.0 ? V : 1;
+    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * n_grids * C * M3) : NULL;
     int rc = 0, done = 0;
     double prev_err = 0.0;
     if (!img || !y || !delta || !rows || !cols || !ones_n || !mask || !inside ||
@@ -931,17 +1041,19 @@ int orc_reconstruct_ext(const orc_grid *g, const orc_camera *cams, int32_t V, in
     }
     if (rp->mode == 0 || rp->mode == 2) {
         for (long i = 0; i < N; ++i) ones_n[i] = 1.0;
-        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, rows, NULL);
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, 0, rows, NULL);
         if (rc) goto done;
         rc = orc_backproject_adjoint(g, cams, V, 1, step_vox, sig, mask, cols);
         if (rc) goto done;
     }
     for (int it = 0; it < iters; ++it) {
         if (S) {
-            rc = orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
+            rc = phase_g != 0.0
+                     ? orc_inscatter_phase(g, cams, V, C, em_io, sig, s_res, n_dirs, s_step, phase_g, S)
+                     : orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
             if (rc) goto done;
         }
-        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, img, NULL);
+        rc = orc_render(g, cams, V, C, step_vox, albedo, background, em_io, sig, s_res, S, phase_g != 0.0, img, NULL);
         if (rc) goto done;
         double r2 = 0.0, cnt = 0.0;
         for (int v = 0; v < V; ++v)
@@ -1137,7 +1249,7 @@ int orc_temperature_fit(const orc_grid *g, const orc_camera *cams, int32_t V, do
     for (int it = 0; it < iters; ++it) {
         orc_temp_map(tp, lut, T_io, N, tmp, sig);
         memcpy(eps, tmp + (long)tp->channel * N, sizeof(double) * N);
-        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, eps, sig, 0, NULL, img, NULL);
+        rc = orc_render(g, cams, V, 1, step_vox, 0.0, 0.0, eps, sig, 0, NULL, 0, img, NULL);
         if (rc) goto done;
         double r2 = 0.0;
         for (int v = 0; v < V; ++v)

@@ -78,13 +78,10 @@ def test_batched_steps_match_each_job_alone():
         held = [(dev(F), dev(sig)) for F, sig in inputs]
         for p, (Fd, sd) in zip(plans, held):
             p.job_begin(Fd, sd, torch.zeros((3,) + p.vol_shape, device="cuda"))
-        # a ragged mix: plan 2 joins one step late and leaves one step late
-        rte().job_step(plans[:2])
-        rte().job_step(plans)
-        rte().job_step(plans[1:])
-        rte().job_step([plans[2], plans[0]])
-        rte().job_step(plans)
-        rte().job_step([plans[1], plans[0]])
+        # a ragged mix, five steps per plan: plan 2 joins one step late and
+        # leaves one step late, and the first plan of a step varies
+        for group in ([0, 1], [0, 1, 2], [1, 2], [2, 0], [0, 1, 2], [1, 0], [2]):
+            rte().job_step([plans[i] for i in group])
         mixed = []
         for p in plans:
             out = torch.empty((3,) + p.vol_shape, device="cuda")

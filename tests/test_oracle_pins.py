@@ -570,3 +570,152 @@ def test_variant_reconstruction_properties():
     c, _, _ = oracle.reconstruct_ext(g, rig, F, sig, x0, 2, mode="paper", g_sigma=0.0)
     np.testing.assert_allclose(c, oracle.reconstruct(g, rig, F, sig, x0, 2, mode="paper"),
                                rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------- anisotropic phase function (Eq. 9)
+def rig_from_centres(centres, targets, W=9, H=7):
+    """Pinhole cameras at `centres`, each looking at its target."""
+    Rs, ts = [], []
+    for eye, tgt in zip(centres, targets):
+        f = np.asarray(tgt, float) - np.asarray(eye, float)
+        up = np.array([0.0, 0.0, 1.0]) if abs(f[2]) < 0.9 * np.linalg.norm(f) else np.array([1.0, 0.0, 0.0])
+        R, t = synth._look_at(eye, tgt, up)
+        Rs.append(R)
+        ts.append(t)
+    V = len(Rs)
+    return synth.Rig(np.full(V, 8.0), np.full(V, 8.0), np.full(V, W / 2), np.full(V, H / 2),
+                     np.array(Rs), np.array(ts), W, H)
+
+
+def test_inscatter_phase_at_g0_is_the_isotropic_grid_for_every_view():
+    g = synth.Grid(7, 6, 8)
+    rng = np.random.default_rng(5)
+    em, sig = rng.uniform(0, 1, size=(2,) + g.shape_zyx), rng.uniform(0, 3, size=g.shape_zyx)
+    rig = small_rig(V=3)
+    iso = oracle.inscatter(g, em, sig, s_res=5, n_dirs=24)
+    per = oracle.inscatter(g, em, sig, s_res=5, n_dirs=24, rig=rig, per_view=True)
+    assert per.shape == (3, 2, 5, 5, 5)
+    for v in range(3):  # sums in another order: equal up to rounding
+        np.testing.assert_allclose(per[v], iso, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("phase_g", [0.6, -0.35])
+def test_inscatter_phase_closed_form_without_extinction(phase_g):
+    """sigma = 0, constant eps: the radiance arriving from u_d is eps times the
+    exit distance along u_d, so S_v(p) is the phase-weighted mean of eps*l_d
+    with the weights of Eq. 9 at w = (o_v - p)/|o_v - p| (towards the camera)
+    and w_i = u_d."""
+    g = synth.Grid(6, 6, 6)
+    eps, M, nd = 0.8, 5, 20
+    rig = small_rig(V=2)
+    S = oracle.inscatter(g, np.full((1, 6, 6, 6), eps), np.zeros((6, 6, 6)), s_res=M, n_dirs=nd,
+                         phase_g=phase_g, rig=rig)
+    dirs = fibonacci(nd)
+    centres = rig.centres()
+    for v in range(2):
+        for (mz, my, mx) in [(2, 2, 2), (0, 1, 3), (4, 4, 0), (1, 3, 2)]:
+            p = np.array([mx, my, mz]) / (M - 1)
+            ell = np.array([exit_length(p, u) for u in dirs])
+            ell = np.where(np.isfinite(ell), ell, 0)
+            w = (centres[v] - p) / np.linalg.norm(centres[v] - p)
+            W = (1 - phase_g ** 2) / (4 * np.pi * (1 + phase_g ** 2 + 2 * phase_g * dirs @ w) ** 1.5)
+            ref = (W * eps * ell).sum() / W.sum()
+            assert abs(S[v, 0, mz, my, mx] - ref) <= 1e-12 * ref
+
+
+def test_inscatter_phase_forward_and_backward_scattering():
+    """A bright source behind the node (seen from view 0) and in front of it
+    (seen from view 1, on the opposite side): forward scattering (g > 0)
+    brightens the light scattered towards view 0 and dims it towards view 1;
+    backward scattering (g < 0) does the opposite (Eq. 9: g > 0 forward)."""
+    g = synth.Grid(13, 13, 13)
+    xs = np.linspace(0, 1, 13)
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    src = np.exp(-(((X - 0.9) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2) / (2 * 0.06 ** 2)))
+    em = src[None] * 5.0
+    sig = np.full(g.shape_zyx, 0.05)
+    # view 0 on the -x side looks along +x through the centre towards the source
+    rig = rig_from_centres([(-2.5, 0.5, 0.5), (3.5, 0.5, 0.5)], [(0.5, 0.5, 0.5)] * 2)
+    S = {gg: oracle.inscatter(g, em, sig, s_res=5, n_dirs=64, phase_g=gg, rig=rig, per_view=True)
+         for gg in (-0.6, 0.0, 0.6)}
+    c = (slice(None), 0, 2, 2, 2)  # centre node
+    fwd, iso, bwd = S[0.6][c], S[0.0][c], S[-0.6][c]
+    assert fwd[0] > 1.5 * iso[0] and iso[0] > 1.5 * bwd[0]     # view 0: source behind the node
+    assert fwd[1] < iso[1] / 1.5 and iso[1] < bwd[1] / 1.5     # view 1: source in front of it
+    np.testing.assert_allclose(iso[0], iso[1], rtol=1e-14)
+
+
+def test_inscatter_phase_sharp_lobe_picks_the_aligned_direction():
+    """|g| -> 1: the phase weights concentrate on the Fibonacci direction
+    aligned with the view (g -> 1: u_d = the march direction from the camera
+    through p; g -> -1: u_d pointing from p to the camera), so S_v(p) -> eps *
+    l_d(p) for that direction (sigma = 0, constant eps)."""
+    g = synth.Grid(6, 6, 6)
+    eps, M, nd = 1.3, 5, 32
+    dirs = fibonacci(nd)
+    p = np.array([0.25, 0.5, 0.75])
+    d_f, d_b = 5, 21
+    rig = rig_from_centres([p - 3 * dirs[d_f], p + 3 * dirs[d_b]], [p, p])
+    m = (3, 2, 1)  # node (mz, my, mx) at p
+    em, sig = np.full((1, 6, 6, 6), eps), np.zeros((6, 6, 6))
+    Sf = oracle.inscatter(g, em, sig, s_res=M, n_dirs=nd, phase_g=0.999, rig=rig)
+    Sb = oracle.inscatter(g, em, sig, s_res=M, n_dirs=nd, phase_g=-0.999, rig=rig)
+    assert abs(Sf[0, 0][m] - eps * exit_length(p, dirs[d_f])) <= 1e-5 * Sf[0, 0][m]
+    assert abs(Sb[1, 0][m] - eps * exit_length(p, dirs[d_b])) <= 1e-5 * Sb[1, 0][m]
+
+
+def test_render_takes_each_views_own_grid():
+    """Per-view in-scatter grids of constant values c_v in a constant medium:
+    view v follows Beer-Lambert with j = eps + albedo sigma c_v."""
+    g = synth.Grid(6, 5, 7)
+    rig = small_rig(V=3, W=17, H=9)
+    eps, sig, albedo = 0.4, 1.7, 0.3
+    cv = np.array([0.2, 1.1, 2.5])
+    S = np.broadcast_to(cv[:, None, None, None, None], (3, 1, 4, 4, 4)).copy()
+    img = oracle.render(g, rig, np.full((1, 7, 5, 6), eps), np.full((7, 5, 6), sig), albedo=albedo,
+                        inscatter=S)
+    for v in range(3):
+        _, _, tn, tf, hit = chords(rig, v)
+        j = eps + albedo * sig * cv[v]
+        ref = np.where(hit, j / sig * (-np.expm1(-sig * (tf - tn))), 0.0)
+        np.testing.assert_allclose(img[v, 0], ref, rtol=1e-12, atol=1e-14)
+
+
+def test_render_gradient_with_per_view_grids_matches_finite_differences():
+    g = synth.Grid(6, 5, 5)
+    rig = synth.ring_rig(3, 9, 8, radius=2.2, elevation_jitter_deg=15, seed=4)
+    rng = np.random.default_rng(2)
+    em = rng.uniform(0.2, 1.0, size=(2,) + g.shape_zyx)
+    sig = rng.uniform(0.5, 3.0, size=g.shape_zyx)
+    S = rng.uniform(0.1, 0.8, size=(3, 2, 4, 4, 4))
+    F = rng.uniform(0.0, 0.3, size=(3, 2, 8, 9))
+    kw = dict(albedo=0.4, inscatter=S)
+    loss = lambda e, s: 0.5 * ((oracle.render(g, rig, e, s, **kw) - F) ** 2).sum()
+    de, dsg = oracle.render_grad(g, rig, em, sig, oracle.render(g, rig, em, sig, **kw) - F, **kw)
+    h = 1e-6
+    for idx in [(2, 3, 3), (1, 2, 4), (3, 1, 2)]:
+        s1, s2 = sig.copy(), sig.copy()
+        s1[idx] += h
+        s2[idx] -= h
+        fd = (loss(em, s1) - loss(em, s2)) / (2 * h)
+        assert abs(fd - dsg[idx]) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_reconstruct_with_phase_function_keeps_the_true_volume():
+    """Frames rendered with Henyey-Greenstein in-scattering of the true
+    volume: a reconstruction started at the truth with the same phase
+    function has zero residual and stays there; started from zero it
+    approaches the truth."""
+    g = synth.Grid(8, 8, 8)
+    rig = small_rig(V=4, W=12, H=12)
+    rng = np.random.default_rng(9)
+    em = rng.uniform(0.1, 1.0, size=(1,) + g.shape_zyx)
+    sig = rng.uniform(0.2, 1.5, size=g.shape_zyx)
+    kw = dict(albedo=0.4, s_res=4, n_dirs=16)
+    S = oracle.inscatter(g, em, sig, s_res=4, n_dirs=16, phase_g=0.5, rig=rig)
+    F = oracle.render(g, rig, em, sig, albedo=0.4, inscatter=S)
+    out, res = oracle.reconstruct(g, rig, F, sig, em, 2, phase_g=0.5, return_residuals=True, **kw)
+    assert res.max() <= 1e-24
+    np.testing.assert_allclose(out, em, rtol=1e-12, atol=1e-13)
+    iso = oracle.reconstruct(g, rig, F, sig, em, 1, phase_g=0.0, return_residuals=True, **kw)[1]
+    assert iso[0] > 1e-8  # the isotropic model does not explain these frames
