@@ -42,6 +42,9 @@ def bytes_per_sample(C: int, scatter: bool):
 
 WORKLOADS = {
     "colour": dict(n=128, views=8, W=512, H=512, C=3, albedo=0.3, M=32, dirs=32, iters=20),
+    # the colour workload with Henyey-Greenstein in-scattering (g = 0.5, one
+    # in-scatter grid per view)
+    "colour_hg": dict(n=128, views=8, W=512, H=512, C=3, albedo=0.3, M=32, dirs=32, iters=20, phase_g=0.5),
     "temperature": dict(n=128, views=8, W=512, H=512, C=1, albedo=0.0, M=0, dirs=32, iters=30),
     "tiny": dict(n=32, views=4, W=64, H=64, C=1, albedo=0.0, M=0, dirs=32, iters=5),
     # gradient-based reconstruction: one step = forward march + adjoint march +
@@ -91,7 +94,8 @@ def cpu_baseline(g, rig, em, sig, frames, wl, views):
     t0 = time.perf_counter()
     S = None
     if wl["albedo"] > 0:
-        S = oracle.inscatter(g, em64, sig64, s_res=wl["M"], n_dirs=wl["dirs"])
+        S = oracle.inscatter(g, em64, sig64, s_res=wl["M"], n_dirs=wl["dirs"], phase_g=wl.get("phase_g", 0.0),
+                             rig=sub)
     I, R = oracle.render(g, sub, em64, sig64, albedo=wl["albedo"], inscatter=S, rowsum=True)
     y = np.where(R[:, None] > 0, (F - I) / np.where(R[:, None] > 0, R[:, None], 1.0), 0.0)
     oracle.backproject_adjoint(g, sub, sig64, y)
@@ -142,7 +146,7 @@ def main():
     if args.workload == "serve":
         return run_serve(args, wl)
     print(f"[bench] workload {args.workload}: building inputs", file=sys.stderr, flush=True)
-    if args.workload in ("colour", "diff"):
+    if args.workload in ("colour", "colour_hg", "diff"):
         g, em, sig = synth.colour_volume(args.seed, n=wl["n"])
     elif args.workload == "tiny":
         g, em, sig = synth.tiny_volume(args.seed, n=wl["n"])
@@ -151,7 +155,8 @@ def main():
     rig = synth.ring_rig(wl["views"], wl["W"], wl["H"])
     C = wl["C"]
     plan = rte.Plan(g, rig, channels=C, step_vox=0.5, albedo=wl["albedo"],
-                    scatter_res=wl["M"], scatter_dirs=wl["dirs"], gradients=args.workload == "diff")
+                    scatter_res=wl["M"], scatter_dirs=wl["dirs"], gradients=args.workload == "diff",
+                    phase_g=wl.get("phase_g", 0.0))
     dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
     if args.workload == "temperature":
         tp = rte.TempParams()
@@ -253,7 +258,9 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['n']}^3 grid, {C} channel(s), "
                                f"{wl['views']} views of {wl['W']}x{wl['H']}, step 0.5 voxel, "
                                f"albedo {wl['albedo']}" + (f", in-scatter {wl['M']}^3 x {wl['dirs']} dirs"
-                                                           if wl["M"] else ""),
+                                                           if wl["M"] else "")
+                               + (f", Henyey-Greenstein g = {wl['phase_g']} (one in-scatter grid per view)"
+                                  if wl.get("phase_g") else ""),
                    "samples_per_step": samples, "hit_rays": plan.hit_rays,
                    "frames_per_s": args.steps / elapsed / wl["iters"]},
         "roofline": roofline,

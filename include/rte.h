@@ -68,10 +68,17 @@ typedef struct {
  *  albedo        sigma_s / sigma_t; 0 disables in-scattering.
  *  background    radiance behind the volume (0: dark capture, Sec. 4.1).
  *  scatter_res   nodes per axis of the in-scatter grid (>= 2 when albedo > 0).
- *  scatter_dirs  directions of the isotropic in-scatter average (1..256).
+ *  scatter_dirs  directions of the in-scatter quadrature (1..256).
  *  scatter_step  in-scatter march step in units of the in-scatter node spacing.
  *  flags         RTE_PLAN_* bits (RTE_PLAN_GRADIENTS: also allocate what
- *                rte_render_backward needs). */
+ *                rte_render_backward needs).
+ *  phase_g       Henyey-Greenstein asymmetry g of Eq. 9, |g| < 1 (0: the
+ *                isotropic phase function the paper uses). With g != 0 the
+ *                in-scattered radiance depends on the direction towards the
+ *                camera, so every view has its own in-scatter grid: the
+ *                in-scatter arrays of rte_inscatter, rte_render and
+ *                rte_render_forward/backward are [V][C][M][M][M] instead of
+ *                [C][M][M][M]. */
 typedef struct {
     int32_t channels;
     float step_vox;
@@ -81,6 +88,7 @@ typedef struct {
     int32_t scatter_dirs;
     float scatter_step;
     int32_t flags;
+    float phase_g;
 } rte_render_params;
 
 #define RTE_PLAN_GRADIENTS 1
@@ -218,12 +226,16 @@ int rte_render_backward(rte_plan *plan, const float *emission, const float *exti
                         const float *grad_images, float *grad_emission, float *grad_extinction,
                         void *stream);
 
-/* In-scattered radiance grid (Eq. 5 third term, isotropic phase function of
- * Eq. 9 at g = 0): at each node p of an M^3 grid over the box, the mean over
- * scatter_dirs spherical-Fibonacci directions u of the emission-absorption
- * march from p along u to the box exit (single scattering).
+/* In-scattered radiance grid (Eq. 5 third term with the phase function of
+ * Eq. 9): at each node p of an M^3 grid over the box, L_d(p) = the
+ * emission-absorption march from p along each of scatter_dirs
+ * spherical-Fibonacci directions u_d to the box exit (single scattering);
+ * phase_g = 0: S(p) = mean_d L_d(p);
+ * phase_g != 0: for each view v, S_v(p) = sum_d W_d L_d(p) / sum_d W_d with
+ * W_d = p(w, u_d) of Eq. 9 and w the unit direction from p to camera v's
+ * centre (a node at a camera centre takes W_d = 1).
  * emission [C][nz][ny][nx], extinction [nz][ny][nx], inscatter [C][M][M][M]
- * (written). */
+ * or [V][C][M][M][M] when phase_g != 0 (written). */
 int rte_inscatter(rte_plan *plan, const float *emission, const float *extinction, float *inscatter,
                   void *stream);
 

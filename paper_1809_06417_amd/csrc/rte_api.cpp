@@ -86,6 +86,7 @@ int validate_config(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
     if (!std::isfinite(params->background))
         return fail(RTE_ERR_INVALID_ARG, "background must be finite");
     if (params->flags & ~RTE_PLAN_GRADIENTS) return fail(RTE_ERR_INVALID_ARG, "unknown plan flags 0x%x", params->flags);
+    if (!(std::fabs(params->phase_g) < 1.0f)) return fail(RTE_ERR_INVALID_ARG, "phase_g must satisfy |g| < 1");
     if (params->albedo > 0.0f || params->scatter_res != 0) {
         if (params->scatter_res < 2 || params->scatter_res > 1024)
             return fail(RTE_ERR_INVALID_ARG, "scatter_res must be in [2, 1024] with albedo > 0");
@@ -169,8 +170,8 @@ std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, co
 }
 
 struct Sizes {
-    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, y, part, cols, lut, mask, inside, err,
-        total;
+    size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, dirs_world, y, part, cols, lut, mask,
+        inside, err, total;
     int part_acc, lut_cap;
 };
 
@@ -190,8 +191,11 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
     s.q = grads ? s.g : 0;
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
-    s.scat = sizeof(float4) * (size_t)std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
+    // one in-scatter grid per view for an anisotropic phase function
+    const size_t grids = (M && params->phase_g != 0.0f) ? (size_t)d.V : 1;
+    s.scat = sizeof(float4) * grids * std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
     s.dirs = sizeof(float4) * kMaxDirs;
+    s.dirs_world = 3 * sizeof(double) * kMaxDirs;
     s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * C * M * M * M : sizeof(float);
     s.y = sizeof(float) * (size_t)d.n_rays * C;
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
@@ -201,6 +205,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.inside = sizeof(int32_t) * (size_t)d.n_nodes;
     s.err = sizeof(float2) * (size_t)d.n_tiles + 2 * sizeof(double) + kBatchBytes;
     s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.scat_part + s.dirs +
+              s.dirs_world +
               s.y + s.part + s.cols + s.lut + s.mask + s.inside + s.err;
     return s;
 }
@@ -291,7 +296,7 @@ void free_plan(rte_plan *p)
     }
     for (auto e : p->event_pool) hipEventDestroy(e);
     void *bufs[] = {p->d_cams, p->d_proj, p->d_rayA, p->d_rayB, p->d_tnear, p->d_tile_kmax,
-                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_scat_part, p->d_dirs, p->d_y, p->d_part,
+                    p->d_tile_off, p->d_tile_order, p->d_g, p->d_q, p->d_vol, p->d_scat, p->d_scat_part, p->d_dirs, p->d_dirs_world, p->d_y, p->d_part,
                     p->d_cols, p->d_lut, p->d_mask, p->d_inside, p->d_err, p->d_err_sum};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -473,7 +478,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     if ((rc = dev_alloc(&p->d_g, full.g, acc)) || (full.q && (rc = dev_alloc(&p->d_q, full.q, acc))) ||
         (rc = dev_alloc(&p->d_vol, full.vol, acc)) ||
         (rc = dev_alloc(&p->d_scat, full.scat, acc)) || (rc = dev_alloc(&p->d_scat_part, full.scat_part, acc)) ||
-        (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) ||
+        (rc = dev_alloc(&p->d_dirs, full.dirs, acc)) || (rc = dev_alloc(&p->d_dirs_world, full.dirs_world, acc)) ||
         (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
         (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)) ||
         (rc = dev_alloc(&p->d_mask, full.mask, acc)) || (rc = dev_alloc(&p->d_inside, full.inside, acc)) ||
@@ -490,15 +495,20 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     // in-scatter directions: spherical Fibonacci, voxel units per world unit
     if (M) {
         std::vector<float4> dirs(kMaxDirs, make_float4(0.f, 0.f, 0.f, 0.f));
+        std::vector<double> world(3 * kMaxDirs, 0.0);
         const int nd = params->scatter_dirs;
         for (int k = 0; k < nd; ++k) {
             const double z = 1.0 - (2.0 * k + 1.0) / (double)nd;
             const double r = std::sqrt(std::max(0.0, 1.0 - z * z));
             const double ph = (double)k * M_PI * (3.0 - std::sqrt(5.0));
-            dirs[k] = make_float4((float)(r * std::cos(ph) / d.h[0]), (float)(r * std::sin(ph) / d.h[1]),
+            world[3 * k] = r * std::cos(ph);
+            world[3 * k + 1] = r * std::sin(ph);
+            world[3 * k + 2] = z;
+            dirs[k] = make_float4((float)(world[3 * k] / d.h[0]), (float)(world[3 * k + 1] / d.h[1]),
                                   (float)(z / d.h[2]), 0.f);
         }
         if (hipMemcpyAsync(p->d_dirs, dirs.data(), full.dirs, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(p->d_dirs_world, world.data(), full.dirs_world, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemsetAsync(p->d_scat, 0, full.scat, s) != hipSuccess)
             return bail(fail(RTE_ERR_HIP, "in-scatter setup failed"));
     }

@@ -87,6 +87,7 @@ struct rte_plan {
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)
     float4 *d_scat = nullptr;       // packed in-scatter grid (rgb, 0)
     float4 *d_dirs = nullptr;       // in-scatter directions, voxel units per world unit
+    double *d_dirs_world = nullptr; // the same directions in the world frame [kMaxDirs][3]
     float *d_scat_part = nullptr;   // per-direction in-scatter sums [dirs][C][M^3]
     float *d_y = nullptr;           // per-pixel residual values [V][C][H][W]
     float *d_part = nullptr;        // per-cell corner partials [8][acc][cells]

@@ -391,6 +391,7 @@ struct RenderArgs {
     int n_launch;               // leading entries of tile_order this launch covers
     const float *vol;
     const float4 *scat;
+    int scat_vstride;    // float4 entries between the grids of consecutive views (0: one grid)
     const float *frames;
     float *out;
     float *g;
@@ -435,7 +436,8 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     int coff[8];
     corner_offsets(nx, nxy, elem, coff);
     const int M = a.M, MM = a.M * a.M;
-    const __amdgpu_buffer_rsrc_t sr = make_rsrc(a.scat, SCAT ? (int64_t)MM * M * 16 : 16);
+    const __amdgpu_buffer_rsrc_t sr =
+        make_rsrc(a.scat + (int64_t)v * a.scat_vstride, SCAT ? (int64_t)MM * M * 16 : 16);
     int soff[8];
     corner_offsets(M, MM, 16, soff);
     float I[C];
@@ -566,6 +568,7 @@ struct GradArgs {
     int n_launch;
     const float *vol;
     const float4 *scat;
+    int scat_vstride;     // as in RenderArgs
     const float *exit_T;  // [V][H][W]
     const float *dI;      // dL/dI [V][C][H][W]
     float *g, *q;         // per-sample outputs, [tile][k][lane]
@@ -607,7 +610,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     int coff[8];
     corner_offsets(nx, nxy, elem, coff);
     const int M = a.M, MM = a.M * a.M;
-    const __amdgpu_buffer_rsrc_t sr = make_rsrc(a.scat, SCAT ? (int64_t)MM * M * 16 : 16);
+    const __amdgpu_buffer_rsrc_t sr =
+        make_rsrc(a.scat + (int64_t)v * a.scat_vstride, SCAT ? (int64_t)MM * M * 16 : 16);
     int soff[8];
     corner_offsets(M, MM, 16, soff);
     float y[C], R[C];
@@ -686,6 +690,12 @@ struct ScatArgs {
     float p_scale[3];    // in-scatter node index -> fine grid coords
     float ds;            // world step
     float inv_ndirs;
+    // anisotropic phase function (one grid per view)
+    const rte_camera *cams;
+    const double *dirs_world;  // [ndirs][3] unit directions, world frame
+    int V;
+    double phase_g;
+    double lo[3], hs[3];       // world position of in-scatter node m: lo + m * hs
 };
 
 // Direction-major march: XCD x (blocks b with b % 8 == x) takes directions
@@ -782,6 +792,62 @@ __global__ __launch_bounds__(kBlock) void inscatter_reduce_kernel(ScatArgs a)
             a.planar[m3 + m] = o.y;
             a.planar[2 * m3 + m] = o.z;
         }
+    }
+}
+
+// Henyey-Greenstein in-scattering (Eq. 9, g != 0): view v sees at node p the
+// incident radiance of every direction u_d weighted by p(w, u_d), w the
+// direction from p to the camera centre (the direction the scattered light
+// travels; u_d points to where the light comes from), the weights normalised
+// over the directions (a radiance equal in every direction scatters into
+// itself). The weights are evaluated in FP64: near |g| -> 1 the denominator
+// 1 + g^2 + 2 g cos is a difference of nearly equal terms. One work-item per
+// (node, view); directions are added in index order.
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_kernel(ScatArgs a)
+{
+    const int m3 = a.M * a.M * a.M;
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    const int v = blockIdx.y;
+    if (m >= m3 || v >= a.V) return;
+    const int M = a.M, mx = m % M, my = (m / M) % M, mz = m / (M * M);
+    const rte_camera &cam = a.cams[v];
+    double w[3], nrm2 = 0.0;
+    const int ms[3] = {mx, my, mz};
+    for (int i = 0; i < 3; ++i) {
+        const double o = -(cam.R[i] * cam.t[0] + cam.R[3 + i] * cam.t[1] + cam.R[6 + i] * cam.t[2]);
+        w[i] = o - (a.lo[i] + (double)ms[i] * a.hs[i]);
+        nrm2 += w[i] * w[i];
+    }
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    const double g = a.phase_g, g2 = g * g;
+    double num[C], den = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) num[c] = 0.0;
+    for (int d = 0; d < a.ndirs; ++d) {
+        double W = 1.0;
+        if (nrm2 > 0.0) {
+            const double *u = a.dirs_world + 3 * d;
+            const double cs = (w[0] * u[0] + w[1] * u[1] + w[2] * u[2]) * inv;
+            const double x = 1.0 + g2 + 2.0 * g * cs;
+            W = (1.0 - g2) / (x * sqrt(x));
+        }
+        den += W;
+#pragma unroll
+        for (int c = 0; c < C; ++c) num[c] += W * (double)a.dpart[(int64_t)(d * C + c) * m3 + m];
+    }
+    float out[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = (float)(num[c] / den);
+    float4 o = make_float4(out[0], 0.f, 0.f, 0.f);
+    if constexpr (C == 3) {
+        o.y = out[1];
+        o.z = out[2];
+    }
+    a.scat[(int64_t)v * m3 + m] = o;
+    if (a.planar) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.planar[(int64_t)(v * C + c) * m3 + m] = out[c];
     }
 }
 
@@ -1306,11 +1372,24 @@ hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipSt
     return hipGetLastError();
 }
 
+// In-scatter grids: one shared grid (isotropic phase function) or one per
+// view (anisotropic), M^3 float4 entries each.
+static int scat_view_stride(const rte_plan *p)
+{
+    const int M = p->params.scatter_res;
+    return (p->params.phase_g != 0.0f && M >= 2) ? M * M * M : 0;
+}
+
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s)
 {
+    // planar [grids][C][M^3] -> packed [grids][M^3] float4, one grid per view
+    // for an anisotropic phase function
     const int64_t m3 = (int64_t)p->params.scatter_res * p->params.scatter_res * p->params.scatter_res;
-    hipLaunchKernelGGL(pack_scatter_kernel, dim3(blocks_for(m3)), dim3(kBlock), 0, s, planar, p->d_scat,
-                       (int)p->params.channels, m3);
+    const int grids = scat_view_stride(p) ? p->V : 1;
+    const int C = p->params.channels;
+    for (int v = 0; v < grids; ++v)
+        hipLaunchKernelGGL(pack_scatter_kernel, dim3(blocks_for(m3)), dim3(kBlock), 0, s,
+                           planar + (int64_t)v * C * m3, p->d_scat + (int64_t)v * m3, C, m3);
     return hipGetLastError();
 }
 
@@ -1360,6 +1439,7 @@ static RenderArgs render_args(const rte_plan *p, int epilogue, const float *fram
     a.tile_off = p->d_tile_off;
     a.vol = p->d_vol;
     a.scat = p->d_scat;
+    a.scat_vstride = scat_view_stride(p);
     a.frames = frames;
     a.out = out;
     a.g = p->d_g;
@@ -1425,12 +1505,26 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     a.dirs_per_xcd = (a.ndirs + 7) / 8;
     const int nb = 8 * a.dirs_per_xcd * a.blocks_per_dir;
     const int64_t m3 = (int64_t)a.M * a.M * a.M;
+    const bool phase = scat_view_stride(p) != 0;
+    if (phase) {
+        a.cams = p->d_cams;
+        a.dirs_world = p->d_dirs_world;
+        a.V = p->V;
+        a.phase_g = (double)p->params.phase_g;
+        for (int i = 0; i < 3; ++i) {
+            a.lo[i] = p->grid.bbox_min[i];
+            a.hs[i] = (p->grid.bbox_max[i] - p->grid.bbox_min[i]) / (double)(a.M - 1);
+        }
+    }
+    const dim3 rgrid((unsigned)blocks_for(m3), phase ? (unsigned)p->V : 1u);
     if (p->params.channels == 3) {
         hipLaunchKernelGGL(inscatter_march_kernel<3>, dim3(nb), dim3(kBlock), 0, s, a);
-        hipLaunchKernelGGL(inscatter_reduce_kernel<3>, dim3(blocks_for(m3)), dim3(kBlock), 0, s, a);
+        if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<3>, rgrid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(inscatter_reduce_kernel<3>, rgrid, dim3(kBlock), 0, s, a);
     } else {
         hipLaunchKernelGGL(inscatter_march_kernel<1>, dim3(nb), dim3(kBlock), 0, s, a);
-        hipLaunchKernelGGL(inscatter_reduce_kernel<1>, dim3(blocks_for(m3)), dim3(kBlock), 0, s, a);
+        if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<1>, rgrid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(inscatter_reduce_kernel<1>, rgrid, dim3(kBlock), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1446,6 +1540,7 @@ hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float
     a.n_launch = p->n_active_tiles;
     a.vol = p->d_vol;
     a.scat = p->d_scat;
+    a.scat_vstride = scat_view_stride(p);
     a.exit_T = exit_T;
     a.dI = dI;
     a.g = p->d_g;

@@ -48,7 +48,8 @@ class Grid(ct.Structure):
 class RenderParams(ct.Structure):
     _fields_ = [("channels", ct.c_int32), ("step_vox", ct.c_float), ("albedo", ct.c_float),
                 ("background", ct.c_float), ("scatter_res", ct.c_int32),
-                ("scatter_dirs", ct.c_int32), ("scatter_step", ct.c_float), ("flags", ct.c_int32)]
+                ("scatter_dirs", ct.c_int32), ("scatter_step", ct.c_float), ("flags", ct.c_int32),
+                ("phase_g", ct.c_float)]
 
 
 class ReconParams(ct.Structure):
@@ -158,11 +159,12 @@ def _cams(rig):
 
 
 def _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step,
-            flags=0):
+            flags=0, phase_g=0.0):
     p = RenderParams()
     p.channels, p.step_vox, p.albedo, p.background = int(channels), step_vox, albedo, background
     p.scatter_res, p.scatter_dirs, p.scatter_step = int(scatter_res), int(scatter_dirs), scatter_step
     p.flags = int(flags)
+    p.phase_g = float(phase_g)
     return p
 
 
@@ -188,10 +190,10 @@ def _ptr(t, shape=None, name="tensor"):
 
 
 def workspace_bytes(grid, rig, channels=1, step_vox=0.5, albedo=0.0, background=0.0, scatter_res=0,
-                    scatter_dirs=32, scatter_step=0.5, gradients=False):
+                    scatter_dirs=32, scatter_step=0.5, gradients=False, phase_g=0.0):
     cams, V = _cams(rig)
     p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step,
-                RTE_PLAN_GRADIENTS if gradients else 0)
+                RTE_PLAN_GRADIENTS if gradients else 0, phase_g)
     return int(lib().rte_plan_workspace_bytes(ct.byref(_grid(grid)), cams, V, ct.byref(p)))
 
 
@@ -200,17 +202,18 @@ class Plan:
 
     def __init__(self, grid, rig, channels=1, step_vox=0.5, albedo=0.0, background=0.0,
                  scatter_res=0, scatter_dirs=32, scatter_step=0.5, hbm_budget_bytes=0,
-                 gradients=False):
+                 gradients=False, phase_g=0.0):
         import torch
         self._h = None
         self.grid = grid
         self.channels = int(channels)
         self.V, self.H, self.W = int(len(rig.fx)), int(rig.height), int(rig.width)
         self.scatter_res = int(scatter_res)
+        self.phase_g = float(phase_g)
         cams, V = _cams(rig)
         self.gradients = bool(gradients)
         self._p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs,
-                          scatter_step, RTE_PLAN_GRADIENTS if gradients else 0)
+                          scatter_step, RTE_PLAN_GRADIENTS if gradients else 0, phase_g)
         h = ct.c_void_p()
         torch.cuda.init()
         _check(lib().rte_plan_create(ct.byref(h), ct.byref(_grid(grid)), cams, V,
@@ -228,6 +231,13 @@ class Plan:
 
     def img_shape(self, C=None):
         return (self.V, self.channels if C is None else C, self.H, self.W)
+
+    @property
+    def scat_shape(self):
+        """[C, M, M, M], or [V, C, M, M, M] (one grid per view) when phase_g != 0."""
+        M = self.scatter_res
+        one = (self.channels, M, M, M)
+        return (self.V,) + one if self.phase_g != 0.0 and M >= 2 else one
 
     def _new(self, shape, dtype=None):
         import torch
@@ -248,7 +258,7 @@ class Plan:
         M = self.scatter_res
         _check(lib().rte_render(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
                                 _ptr(extinction, self.vol_shape, "extinction"),
-                                _ptr(inscatter, (C, M, M, M), "inscatter"),
+                                _ptr(inscatter, self.scat_shape, "inscatter"),
                                 _ptr(out, self.img_shape(), "images"), _stream()))
         return out
 
@@ -259,7 +269,7 @@ class Plan:
         exit_T = self._new((self.V, self.H, self.W))
         _check(lib().rte_render_forward(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
                                         _ptr(extinction, self.vol_shape, "extinction"),
-                                        _ptr(inscatter, (C, M, M, M), "inscatter"),
+                                        _ptr(inscatter, self.scat_shape, "inscatter"),
                                         _ptr(out), _ptr(exit_T), _stream()))
         return out, exit_T
 
@@ -270,17 +280,17 @@ class Plan:
         g_sig = self._new(self.vol_shape)
         _check(lib().rte_render_backward(
             self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
-            _ptr(extinction, self.vol_shape, "extinction"), _ptr(inscatter, (C, M, M, M), "inscatter"),
+            _ptr(extinction, self.vol_shape, "extinction"), _ptr(inscatter, self.scat_shape, "inscatter"),
             _ptr(exit_T, (self.V, self.H, self.W), "exit_T"),
             _ptr(grad_images, self.img_shape(), "grad_images"), _ptr(g_em), _ptr(g_sig), _stream()))
         return g_em, g_sig
 
     def inscatter(self, emission, extinction, out=None):
-        C, M = self.channels, self.scatter_res
-        out = self._new((C, M, M, M)) if out is None else out
+        C = self.channels
+        out = self._new(self.scat_shape) if out is None else out
         _check(lib().rte_inscatter(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
                                    _ptr(extinction, self.vol_shape, "extinction"),
-                                   _ptr(out, (C, M, M, M), "inscatter"), _stream()))
+                                   _ptr(out, self.scat_shape, "inscatter"), _stream()))
         return out
 
     def backproject(self, extinction, residual, mode="adjoint", alpha_l=1e-3, alpha_d=1.0,

@@ -63,6 +63,9 @@ def test_workspace_bytes_host_only():
     (lambda g, c, p: setattr(c[1], "width", 5), "image size"),
     (lambda g, c, p: setattr(c[0], "fx", 0.0), "intrinsics"),
     (lambda g, c, p: (setattr(p, "albedo", 0.3), setattr(p, "scatter_res", 1)), "scatter_res"),
+    (lambda g, c, p: setattr(p, "phase_g", 1.0), "phase_g"),
+    (lambda g, c, p: setattr(p, "phase_g", -1.5), "phase_g"),
+    (lambda g, c, p: setattr(p, "phase_g", float("nan")), "phase_g"),
 ])
 def test_invalid_arguments_rejected(mutate, msg):
     grid, cams, V, p = _args()
@@ -74,6 +77,15 @@ def test_invalid_arguments_rejected(mutate, msg):
     assert rc == rte.RTE_ERR_INVALID_ARG
     assert msg in L.rte_last_error().decode()
     assert not h.value
+
+
+def test_phase_function_holds_one_in_scatter_grid_per_view():
+    grid, cams, V, p = _args(channels=3, albedo=0.3, scatter_res=16)
+    L = rte.lib()
+    iso = L.rte_plan_workspace_bytes(ct.byref(grid), cams, V, ct.byref(p))
+    p.phase_g = 0.5
+    hg = L.rte_plan_workspace_bytes(ct.byref(grid), cams, V, ct.byref(p))
+    assert hg - iso == (V - 1) * 16 ** 3 * 16
 
 
 def test_budget_rejected_before_allocation():
