@@ -185,6 +185,22 @@ void rte_plan_destroy(rte_plan *plan);
  * counts) and number of rays that hit the volume. */
 int rte_plan_counts(const rte_plan *plan, uint64_t *samples, uint64_t *hit_rays);
 
+/* Volume dimensions from the camera rig (Sec. 4.2, volume dimensions): the
+ * eight corners of the box [bbox_min, bbox_max] are projected into every
+ * view; along each axis a, n_max[a] = the largest pixel span max(|du|, |dv|)
+ * of the four box edges parallel to a over all views, and the volume gets
+ * ceil(n_max[a] / alpha) voxels (alpha = 1.5 in the paper), i.e. one key
+ * point more, written to grid (with the box). An edge with an end point on
+ * or behind a camera's image plane (camera z <= 0) does not count for that
+ * camera. With the paper's sampling step of one voxel edge, pass
+ * step_vox = 1 to rte_plan_create. Host only: no device work.
+ * cams [ncams] (image sizes are not used), grid (written), n_max [3]
+ * (written, may be NULL). Errors: RTE_ERR_INVALID_ARG for null pointers,
+ * ncams < 1, alpha <= 0, an empty box, or an axis none of whose edges
+ * projects into any view; grid is untouched then. */
+int rte_suggest_grid(const rte_camera *cams, int32_t ncams, const double bbox_min[3],
+                     const double bbox_max[3], double alpha, rte_grid *grid, double *n_max);
+
 /* Export the ray table: t_near, t_far (world units along the unit ray
  * direction) and segment count K per pixel, [view][v][u] device arrays.
  * Rays that miss get K = 0 and t_near = t_far = 0. */

@@ -15,7 +15,7 @@ __all__ = [
     "lib", "ray_table", "render", "inscatter", "backproject_adjoint", "backproject_paper",
     "reconstruct", "planck", "band_radiance", "TempParams", "temp_lut", "temp_map",
     "temp_invert", "temperature_fit", "num_threads", "render_grad", "philox4x32_10",
-    "sample_gain", "flame_mask", "visual_hull", "reconstruct_ext",
+    "sample_gain", "flame_mask", "visual_hull", "reconstruct_ext", "suggest_grid",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,11 +90,23 @@ def lib():
         _lib.orc_temperature_fit.argtypes = [P(_Grid), P(_Camera), i32, d, P(_TempParams), dp, dp,
                                              dp, i32, d, dp]
         _lib.orc_num_threads.restype = ct.c_int
+        _lib.orc_suggest_grid.argtypes = [P(_Camera), i32, dp, dp, d, P(ct.c_int32), dp]
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def suggest_grid(rig, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), alpha=1.5):
+    """Voxels per axis (x, y, z) and the projected edge spans n_max (pixels)
+    for the box [lo, hi] seen by `rig` (Sec. 4.2)."""
+    lo_a, hi_a = np.array(lo, dtype=np.float64), np.array(hi, dtype=np.float64)
+    vox = (ct.c_int32 * 3)()
+    nmax = np.zeros(3)
+    _check(lib().orc_suggest_grid(_cams(rig), rig.n_views, _dp(lo_a), _dp(hi_a), float(alpha), vox,
+                                  _dp(nmax)), "suggest_grid")
+    return tuple(int(v) for v in vox), nmax
 
 
 def _dp(a):

@@ -1278,4 +1278,53 @@ done:
     return rc;
 }
 
+/* ------------------------------------------ volume dimensions (Sec. 4.2) */
+
+/* Volume dimensions from the cameras (Sec. 4.2): project the eight vertices
+ * of the box [lo, hi] into every image; each of the twelve box edges spans
+ * |du| and |dv| pixels; n_max[a] = the largest of these spans over the four
+ * edges along axis a and over all views, and the volume gets
+ * ceil(n_max[a] / alpha) voxels along a (alpha = 1.5 in the paper), i.e.
+ * one key point more. An edge with an end point on or behind a camera's
+ * image plane (z_c <= 0) is skipped for that camera. Returns -1 when no
+ * edge along some axis projects into any view. voxels [3] (x, y, z),
+ * n_max [3] (optional). */
+int orc_suggest_grid(const orc_camera *cams, int32_t V, const double lo[3], const double hi[3], double alpha,
+                     int32_t voxels[3], double *n_max)
+{
+    if (V < 1 || !(alpha > 0.0)) return -1;
+    double best[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < V; ++v) {
+        const orc_camera *c = &cams[v];
+        double uv[8][2];
+        int front[8];
+        for (int corner = 0; corner < 8; ++corner) {
+            double x[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1], (corner & 4) ? hi[2] : lo[2]};
+            double xc[3];
+            for (int r = 0; r < 3; ++r)
+                xc[r] = c->R[3 * r] * x[0] + c->R[3 * r + 1] * x[1] + c->R[3 * r + 2] * x[2] + c->t[r];
+            front[corner] = xc[2] > 0.0;
+            uv[corner][0] = front[corner] ? c->fx * (xc[0] / xc[2]) + c->cx : 0.0;
+            uv[corner][1] = front[corner] ? c->fy * (xc[1] / xc[2]) + c->cy : 0.0;
+        }
+        /* the edge along axis a joins corners that differ only in bit a */
+        for (int a = 0; a < 3; ++a)
+            for (int corner = 0; corner < 8; ++corner) {
+                if (corner & (1 << a)) continue;
+                int other = corner | (1 << a);
+                if (!front[corner] || !front[other]) continue;
+                double du = fabs(uv[other][0] - uv[corner][0]), dv = fabs(uv[other][1] - uv[corner][1]);
+                double span = du > dv ? du : dv;
+                if (span > best[a]) best[a] = span;
+            }
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!(best[a] > 0.0)) return -1;
+        double n = ceil(best[a] / alpha);
+        voxels[a] = n < 1.0 ? 1 : (int32_t)n;
+        if (n_max) n_max[a] = best[a];
+    }
+    return 0;
+}
+
 int orc_num_threads(void) { return n_threads(); }

@@ -537,6 +537,55 @@ size_t rte_plan_device_bytes(const rte_plan *plan) { return plan ? plan->device_
 
 void rte_plan_destroy(rte_plan *plan) { free_plan(plan); }
 
+int rte_suggest_grid(const rte_camera *cams, int32_t ncams, const double bbox_min[3], const double bbox_max[3],
+                     double alpha, rte_grid *grid, double *n_max)
+{
+    if (!cams || !bbox_min || !bbox_max || !grid) return fail(RTE_ERR_INVALID_ARG, "null argument");
+    if (ncams < 1) return fail(RTE_ERR_INVALID_ARG, "need at least one camera");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(RTE_ERR_INVALID_ARG, "alpha must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(bbox_min[a]) || !std::isfinite(bbox_max[a]) || !(bbox_max[a] > bbox_min[a]))
+            return fail(RTE_ERR_INVALID_ARG, "bbox axis %d is empty or not finite", a);
+    double span[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < ncams; ++v) {
+        const rte_camera &c = cams[v];
+        // corner index bits: x (1), y (2), z (4); camera coordinates of each
+        double pc[8][3];
+        for (int k = 0; k < 8; ++k) {
+            const double w[3] = {(k & 1) ? bbox_max[0] : bbox_min[0], (k & 2) ? bbox_max[1] : bbox_min[1],
+                                 (k & 4) ? bbox_max[2] : bbox_min[2]};
+            for (int r = 0; r < 3; ++r) pc[k][r] = c.R[3 * r] * w[0] + c.R[3 * r + 1] * w[1] + c.R[3 * r + 2] * w[2] + c.t[r];
+        }
+        for (int axis = 0; axis < 3; ++axis) {
+            const int bit = 1 << axis;
+            for (int k = 0; k < 8; ++k) {
+                if (k & bit) continue;
+                const double *p0 = pc[k], *p1 = pc[k | bit];
+                if (!(p0[2] > 0.0) || !(p1[2] > 0.0)) continue;  // crosses or lies behind the image plane
+                const double du = std::fabs((c.fx * (p1[0] / p1[2]) + c.cx) - (c.fx * (p0[0] / p0[2]) + c.cx));
+                const double dv = std::fabs((c.fy * (p1[1] / p1[2]) + c.cy) - (c.fy * (p0[1] / p0[2]) + c.cy));
+                span[axis] = std::max(span[axis], std::max(du, dv));
+            }
+        }
+    }
+    int32_t nodes[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!(span[a] > 0.0)) return fail(RTE_ERR_INVALID_ARG, "no edge along axis %d projects into any view", a);
+        const double vox = std::ceil(span[a] / alpha);
+        if (vox > 65535.0) return fail(RTE_ERR_INVALID_ARG, "axis %d would need %.0f voxels", a, vox);
+        nodes[a] = (int32_t)std::max(vox, 1.0) + 1;
+    }
+    grid->nx = nodes[0];
+    grid->ny = nodes[1];
+    grid->nz = nodes[2];
+    for (int a = 0; a < 3; ++a) {
+        grid->bbox_min[a] = bbox_min[a];
+        grid->bbox_max[a] = bbox_max[a];
+        if (n_max) n_max[a] = span[a];
+    }
+    return ok();
+}
+
 int rte_plan_counts(const rte_plan *plan, uint64_t *samples, uint64_t *hit_rays)
 {
     if (int rc = check_plan(plan)) return rc;

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "LIB_PATH", "lib", "RteError", "Plan", "TempParams", "plan_create", "render", "inscatter",
     "backproject", "reconstruct", "reconstruct_temperature", "temperature_map",
-    "temperature_invert", "KERNELS", "UPDATES", "job_step",
+    "temperature_invert", "KERNELS", "UPDATES", "job_step", "suggest_grid",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
@@ -120,6 +120,8 @@ def lib():
     L.rte_temperature_map.argtypes = [vp, vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_invert.argtypes = [vp, vp, vp, P(_TempParams), vp]
     L.rte_temperature_lut.argtypes = [vp, P(_TempParams), P(ct.c_float), i32]
+    L.rte_suggest_grid.argtypes = [P(Camera), i32, P(ct.c_double), P(ct.c_double), ct.c_double, P(Grid),
+                                   P(ct.c_double)]
     L.rte_job_begin.argtypes = [vp, vp, vp, vp, P(ReconParams), vp]
     L.rte_job_step.argtypes = [P(vp), i32, vp]
     L.rte_job_end.argtypes = [vp, vp, vp]
@@ -423,6 +425,17 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def suggest_grid(rig, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), alpha=1.5):
+    """Key points per axis (nx, ny, nz) for the box [lo, hi] seen by `rig`, and
+    the projected edge spans n_max (pixels) they come from (host only)."""
+    cams, V = _cams(rig)
+    lo_a, hi_a = (ct.c_double * 3)(*lo), (ct.c_double * 3)(*hi)
+    g = Grid()
+    nmax = (ct.c_double * 3)()
+    _check(lib().rte_suggest_grid(cams, V, lo_a, hi_a, float(alpha), ct.byref(g), nmax))
+    return (int(g.nx), int(g.ny), int(g.nz)), tuple(float(x) for x in nmax)
 
 
 def job_step(plans):

@@ -5,6 +5,7 @@ import ctypes as ct
 import os
 import re
 
+import numpy as np
 import pytest
 
 import synth
@@ -117,3 +118,25 @@ def test_workspace_bound_scales_with_samples():
     p.step_vox = 0.125
     b = L.rte_plan_workspace_bytes(ct.byref(grid), cams, V, ct.byref(p))
     assert b > a
+
+
+def test_suggest_grid_matches_oracle_and_rejects_bad_input():
+    """Host-only helper: voxel counts bit-exact against the oracle's
+    independent implementation on seeded rigs (FP64 on both sides)."""
+    import oracle
+    for seed in range(6):
+        rig = synth.ring_rig(3 + seed, 200 + 40 * seed, 150 + 30 * seed, radius=1.5 + 0.3 * seed,
+                             fov_y_deg=40 + 5 * seed, elevation_jitter_deg=15, seed=seed)
+        lo, hi = (-0.1 * seed, 0.0, 0.2), (1.0, 1.0 + 0.1 * seed, 1.1)
+        (nx, ny, nz), nmax = rte.suggest_grid(rig, lo, hi, alpha=1.5)
+        vox, nmax_o = oracle.suggest_grid(rig, lo, hi, alpha=1.5)
+        assert (nx - 1, ny - 1, nz - 1) == vox
+        np.testing.assert_allclose(nmax, nmax_o, rtol=1e-14)
+    L = rte.lib()
+    cams, V = rte._cams(synth.ring_rig(2, 10, 10))
+    g = rte.Grid()
+    lo, hi = (ct.c_double * 3)(0, 0, 0), (ct.c_double * 3)(1, 1, 1)
+    assert L.rte_suggest_grid(cams, V, lo, hi, 0.0, ct.byref(g), None) == rte.RTE_ERR_INVALID_ARG
+    assert L.rte_suggest_grid(cams, 0, lo, hi, 1.5, ct.byref(g), None) == rte.RTE_ERR_INVALID_ARG
+    assert L.rte_suggest_grid(cams, V, hi, lo, 1.5, ct.byref(g), None) == rte.RTE_ERR_INVALID_ARG
+    assert g.nx == 0

@@ -719,3 +719,33 @@ def test_reconstruct_with_phase_function_keeps_the_true_volume():
     np.testing.assert_allclose(out, em, rtol=1e-12, atol=1e-13)
     iso = oracle.reconstruct(g, rig, F, sig, em, 1, phase_g=0.0, return_residuals=True, **kw)[1]
     assert iso[0] > 1e-8  # the isotropic model does not explain these frames
+
+
+# ------------------------------------------- volume dimensions (Sec. 4.2)
+def test_suggest_grid_face_on_camera_closed_form():
+    """A camera facing the unit cube head-on from (0.3, 0.6, -2): edges along
+    x and y of the front face (depth 2) span fx/2 and fy/2 pixels, edges along
+    z (depth 2 -> 3) span f * offset * (1/2 - 1/3) with the largest lateral
+    offsets 0.7 (x) and 0.6 (y). A second camera inside the box sees the back
+    face at depth 0.5 (spans 2 f) while its edges along z, which cross its
+    image plane, are skipped."""
+    o1, o2 = np.array([0.3, 0.6, -2.0]), np.array([0.5, 0.5, 0.5])
+    rig = synth.Rig(np.array([100.0, 10.0]), np.array([120.0, 12.0]), np.array([50.0, 5.0]),
+                    np.array([40.0, 5.0]), np.stack([np.eye(3), np.eye(3)]), np.stack([-o1, -o2]), 100, 80)
+    vox, nmax = oracle.suggest_grid(rig, alpha=1.6)
+    ref = np.array([max(100 / 2, 2 * 10), max(120 / 2, 2 * 12), max(100 * 0.7, 120 * 0.6) * (1 / 2 - 1 / 3)])
+    np.testing.assert_allclose(nmax, ref, rtol=1e-12)
+    assert vox == (32, 38, 8)  # ceil(31.25), ceil(37.5), ceil(7.5)
+    # the inside camera alone: no edge along z projects
+    with pytest.raises(RuntimeError):
+        oracle.suggest_grid(rig.subset([1]), alpha=1.6)
+
+
+def test_suggest_grid_scales_with_resolution_and_alpha():
+    rig = synth.ring_rig(6, 320, 240, radius=2.0, elevation_jitter_deg=8, seed=1)
+    big = synth.ring_rig(6, 640, 480, radius=2.0, elevation_jitter_deg=8, seed=1)
+    (v1, n1), (v2, n2) = oracle.suggest_grid(rig), oracle.suggest_grid(big)
+    np.testing.assert_allclose(n2, 2 * n1, rtol=1e-12)  # twice the pixels per unit length
+    v3, _ = oracle.suggest_grid(rig, alpha=3.0)
+    assert all(a >= b for a, b in zip(v1, v3))
+    assert v3 == tuple(int(np.ceil(n / 3.0)) for n in n1)
