@@ -197,18 +197,24 @@ def _plume_blobs(rng, n_blobs):
     return centres, covs
 
 
+def colour_blobs(seed: int = 0, n_blobs: int = 20):
+    """The plume blobs of the colour workload: (centres, covariances, peaks
+    [B, 4] = RGB emission and extinction) on the unit cube."""
+    rng = np.random.default_rng(seed)
+    centres, covs = _plume_blobs(rng, n_blobs)
+    rgb = np.array([[1.0, rng.uniform(0.4, 0.8), rng.uniform(0.1, 0.3)] for _ in range(n_blobs)])
+    rgb *= rng.uniform(0.5, 1.0, size=(n_blobs, 1))
+    sig_pk = rng.uniform(0.5, 4.0, size=n_blobs)
+    return centres, covs, np.concatenate([rgb, sig_pk[:, None]], axis=1)
+
+
 def colour_volume(seed: int = 0, n: int = 128, n_blobs: int = 20):
     """Colour-intensity workload: 20 anisotropic plume blobs stretched along +z.
     Per-blob RGB emission (1, U[0.4,0.8], U[0.1,0.3]) * U[0.5,1]; per-blob peak
     extinction U[0.5,4] per unit length. Returns (grid, emission [3,n,n,n],
     extinction [n,n,n])."""
-    rng = np.random.default_rng(seed)
     g = Grid(n, n, n)
-    centres, covs = _plume_blobs(rng, n_blobs)
-    rgb = np.array([[1.0, rng.uniform(0.4, 0.8), rng.uniform(0.1, 0.3)] for _ in range(n_blobs)])
-    rgb *= rng.uniform(0.5, 1.0, size=(n_blobs, 1))
-    sig_pk = rng.uniform(0.5, 4.0, size=n_blobs)
-    fields = blob_fields(g, centres, covs, np.concatenate([rgb, sig_pk[:, None]], axis=1))
+    fields = blob_fields(g, *colour_blobs(seed, n_blobs))
     return g, fields[:3].copy(), fields[3].copy()
 
 
