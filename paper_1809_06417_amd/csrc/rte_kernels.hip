@@ -418,7 +418,9 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blk * 4 + wave;
     if (slot >= a.n_launch) return;
-    const int tile = a.tile_order[slot];
+    // every lane of the wave reads the same entry: keep the tile (and so the
+    // view and the per-view in-scatter grid address) in scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(a.tile_order[slot]);
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
@@ -527,7 +529,8 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
 }
 
 template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
-__global__ __launch_bounds__(kBlock) void render_kernel(RenderArgs a)
+__global__ __launch_bounds__(kBlock) void render_kernel(
+    RenderArgs a)
 {
     render_body<C, EMIS, SCAT, WRITE_G, EPI>(a, blockIdx.x);
 }
@@ -542,7 +545,8 @@ __device__ __forceinline__ int batch_job(const int *prefix, int n, int b)
 
 // One launch covering the tiles of several independent jobs (plans).
 template <int C, bool EMIS, bool SCAT, bool WRITE_G, int EPI>
-__global__ __launch_bounds__(kBlock) void render_batch_kernel(const RenderArgs *args, const int *prefix, int n)
+__global__ __launch_bounds__(kBlock) void render_batch_kernel(
+    const RenderArgs *args, const int *prefix, int n)
 {
     const int j = batch_job(prefix, n, blockIdx.x);
     render_body<C, EMIS, SCAT, WRITE_G, EPI>(args[j], blockIdx.x - prefix[j]);
@@ -593,7 +597,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + wave;
     if (slot >= a.n_launch) return;
-    const int tile = a.tile_order[slot];
+    // every lane of the wave reads the same entry: keep the tile (and so the
+    // view and the per-view in-scatter grid address) in scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(a.tile_order[slot]);
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
@@ -1057,13 +1063,15 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
 }
 
 template <int C, int MODE>
-__global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs a)
+__global__ __launch_bounds__(kBlock) void gather_kernel(
+    GatherArgs a)
 {
     gather_body<C, MODE>(a, xcd_remap(blockIdx.x, a.nb8));
 }
 
 template <int C, int MODE>
-__global__ __launch_bounds__(kBlock) void gather_batch_kernel(const GatherArgs *args, const int *prefix, int n)
+__global__ __launch_bounds__(kBlock) void gather_batch_kernel(
+    const GatherArgs *args, const int *prefix, int n)
 {
     const int j = batch_job(prefix, n, blockIdx.x);
     gather_body<C, MODE>(args[j], blockIdx.x - prefix[j]);
