@@ -118,27 +118,48 @@ __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, int voff, int
     return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
 }
 
+template <int C> struct Packed;
+template <> struct Packed<1> { using T = float2; };
+template <> struct Packed<3> { using T = float4; };
+
 // Trilinear sample of a packed volume through a buffer resource: coff holds
-// the byte offsets of the 8 cell corners (uniform across the launch).
+// the byte offsets of the 8 cell corners (uniform across the launch). The
+// corners of the last cell sampled are kept (a march at half a voxel per step
+// stays in one cell for about every other sample): they are reloaded only
+// when the cell changes, and the interpolation is the same as with a fresh
+// load.
+template <int C>
+struct VolCorners {
+    using T = typename Packed<C>::T;
+    int cell = -1;
+    T v[8];
+};
+
 template <int C>
 __device__ __forceinline__ void sample_volume_rsrc(__amdgpu_buffer_rsrc_t r, const int coff[8], int base_bytes,
-                                                   const float w[8], float em[C], float &sig)
+                                                   const float w[8], VolCorners<C> &vc, float em[C], float &sig)
 {
+    if (base_bytes != vc.cell) {
+        vc.cell = base_bytes;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if constexpr (C == 3) vc.v[c] = bload4(r, base_bytes, coff[c]);
+            else vc.v[c] = bload2(r, base_bytes, coff[c]);
+        }
+    }
     sig = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) em[c] = 0.0f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         if constexpr (C == 3) {
-            const float4 v = bload4(r, base_bytes, coff[c]);
-            em[0] = fmaf(w[c], v.x, em[0]);
-            em[1] = fmaf(w[c], v.y, em[1]);
-            em[2] = fmaf(w[c], v.z, em[2]);
-            sig = fmaf(w[c], v.w, sig);
+            em[0] = fmaf(w[c], vc.v[c].x, em[0]);
+            em[1] = fmaf(w[c], vc.v[c].y, em[1]);
+            em[2] = fmaf(w[c], vc.v[c].z, em[2]);
+            sig = fmaf(w[c], vc.v[c].w, sig);
         } else {
-            const float2 v = bload2(r, base_bytes, coff[c]);
-            em[0] = fmaf(w[c], v.x, em[0]);
-            sig = fmaf(w[c], v.y, sig);
+            em[0] = fmaf(w[c], vc.v[c].x, em[0]);
+            sig = fmaf(w[c], vc.v[c].y, sig);
         }
     }
 }
@@ -181,9 +202,6 @@ __device__ __forceinline__ float sample_gain(uint32_t seed_lo, uint32_t seed_hi,
     return fmaf(g_sigma, z, 1.0f);
 }
 
-template <int C> struct Packed;
-template <> struct Packed<1> { using T = float2; };
-template <> struct Packed<3> { using T = float4; };
 
 // Trilinear sample of the packed volume: emission channels and extinction.
 template <int C>
@@ -382,6 +400,36 @@ __global__ __launch_bounds__(kBlock) void pack_scatter_kernel(const float *plana
     out[m] = v;
 }
 
+// In-scatter corners of the coarse cell a ray is in. The coarse grid is
+// several fine cells wide, so consecutive samples mostly stay in one coarse
+// cell: the eight corners are reloaded only when the cell changes (the
+// values and the interpolation order are those of a fresh load).
+struct ScatCorners {
+    int cell = -1;
+    float v[8][3];
+};
+
+__device__ __forceinline__ void scat_sample(const __amdgpu_buffer_rsrc_t &sr, const int soff[8], int sb,
+                                            const float ws[8], ScatCorners &cc, float S[3])
+{
+    if (sb != cc.cell) {
+        cc.cell = sb;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float4 q = bload4(sr, sb, soff[c]);
+            cc.v[c][0] = q.x;
+            cc.v[c][1] = q.y;
+            cc.v[c][2] = q.z;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        S[0] = fmaf(ws[c], cc.v[c][0], S[0]);
+        S[1] = fmaf(ws[c], cc.v[c][1], S[1]);
+        S[2] = fmaf(ws[c], cc.v[c][2], S[2]);
+    }
+}
+
 // ---------------------------------------------------------------- K1 render
 
 struct RenderArgs {
@@ -448,6 +496,8 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     float T = 1.0f, Rsum = 0.0f;
     float *gp = nullptr;
     if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
+    ScatCorners scc;
+    VolCorners<C> vcc;
     for (int k = 0; k < K; ++k) {
         float s, len;
         segment_of(k, K, A.w, a.ds, s, len);
@@ -461,7 +511,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
         tri_weights(fx, fy, fz, w);
         float em[C], sig;
         const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        sample_volume_rsrc<C>(vr, coff, base * elem, w, em, sig);
+        sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sig);
         sig = fmaxf(sig, 0.0f);
         if constexpr (SCAT) {
             int jx, jy, jz;
@@ -473,13 +523,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
             tri_weights(gx, gy, gz, ws);
             const int sb = ((int)(__umul24(jz, MM) + __umul24(jy, M)) + jx) * 16;
             float S[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const float4 q = bload4(sr, sb, soff[c]);
-                S[0] = fmaf(ws[c], q.x, S[0]);
-                S[1] = fmaf(ws[c], q.y, S[1]);
-                S[2] = fmaf(ws[c], q.z, S[2]);
-            }
+            scat_sample(sr, soff, sb, ws, scc, S);
             const float as = a.albedo * sig;
 #pragma unroll
             for (int c = 0; c < C; ++c) em[c] = fmaf(as, S[c], em[c]);
@@ -629,6 +673,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     }
     float *gp = a.g + a.tile_off[tile] + lane;
     float *qp = a.q + a.tile_off[tile] + lane;
+    ScatCorners scc;
+    VolCorners<C> vcc;
     for (int k = K - 1; k >= 0; --k) {
         float s, len;
         segment_of(k, K, A.w, a.ds, s, len);
@@ -642,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
         tri_weights(fx, fy, fz, w);
         float em[C], sraw;
         const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        sample_volume_rsrc<C>(vr, coff, base * elem, w, em, sraw);
+        sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sraw);
         const float sig = fmaxf(sraw, 0.0f);
         float S[3] = {0.f, 0.f, 0.f};
         if constexpr (SCAT) {
@@ -654,13 +700,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
             float ws[8];
             tri_weights(gx, gy, gz, ws);
             const int sb = ((int)(__umul24(jz, MM) + __umul24(jy, M)) + jx) * 16;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const float4 qv = bload4(sr, sb, soff[c]);
-                S[0] = fmaf(ws[c], qv.x, S[0]);
-                S[1] = fmaf(ws[c], qv.y, S[1]);
-                S[2] = fmaf(ws[c], qv.z, S[2]);
-            }
+            scat_sample(sr, soff, sb, ws, scc, S);
             const float as = a.albedo * sig;
 #pragma unroll
             for (int c = 0; c < C; ++c) em[c] = fmaf(as, S[c], em[c]);
@@ -758,7 +798,8 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
         tri_weights(fx, fy, fz, wt);
         float em[C], sig;
         const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        sample_volume_rsrc<C>(vr, coff, base * elem, wt, em, sig);
+        VolCorners<C> vcc;  // samples here are two fine cells apart: no reuse to keep
+        sample_volume_rsrc<C>(vr, coff, base * elem, wt, vcc, em, sig);
         sig = fmaxf(sig, 0.0f);
         float e;
         const float wg = T * len * phi_exp(sig * len, e);
