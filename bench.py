@@ -62,6 +62,38 @@ WORKLOADS = {
 }
 
 
+def inscatter_samples(n: int, M: int, ndirs: int, s_step: float = 0.5) -> int:
+    """March samples of one in-scatter pass on an n^3 unit-cube grid: from each
+    of the M^3 nodes along each spherical-Fibonacci direction to the box exit
+    with steps of s_step coarse spacings (FP32, as the kernel counts them;
+    a count may differ by one where a chord is a whole number of steps)."""
+    import numpy as np
+    k = np.arange(ndirs, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / ndirs
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    ph = k * np.pi * (3.0 - np.sqrt(5.0))
+    h = 1.0 / (n - 1)
+    u = np.stack([r * np.cos(ph), r * np.sin(ph), z], 1) / h          # voxel units per world unit
+    u = u.astype(np.float32)
+    scale = np.float32((n - 1) / (M - 1))
+    p = (np.arange(M, dtype=np.float32) * scale).astype(np.float32)
+    P = np.stack(np.meshgrid(p, p, p, indexing="ij"), -1).reshape(-1, 3)  # node coords (any axis order)
+    top = np.float32(n - 1)
+    ds = np.float32(s_step / (M - 1))
+    total = 0
+    for d in range(ndirs):
+        ell = np.full(P.shape[0], np.inf, dtype=np.float32)
+        for ax in range(3):
+            ua = u[d, ax]
+            if ua > 0:
+                ell = np.minimum(ell, (top - P[:, ax]) / ua)
+            elif ua < 0:
+                ell = np.minimum(ell, -P[:, ax] / ua)
+        ell = np.maximum(ell, np.float32(0.0))
+        total += int(np.where(ell > 0, np.ceil(ell / ds), 0).sum())
+    return total
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for f in ("rte_kernels.hip",):
@@ -223,22 +255,34 @@ def main():
     samples = plan.samples
     value = samples * args.steps / elapsed
     b_render, b_gather = bytes_per_sample(C, wl["albedo"] > 0)
-    cands = {"render": b_render, "gather": b_gather}
+    # algorithmic bytes per launch of each candidate kernel
+    cands = {"render": b_render * samples, "gather": b_gather * samples}
     if args.workload == "diff":
         # the adjoint march re-reads what the render reads; the gradient gather
         # accumulates C emission + 1 extinction values per corner
-        cands = {"render": b_render, "adjoint": b_render, "gather": 8 * (C + 1) * 4}
+        cands = {"render": b_render * samples, "adjoint": b_render * samples,
+                 "gather": 8 * (C + 1) * 4 * samples}
+    scat_samples = None
+    if wl["albedo"] > 0 and wl["M"] >= 2:
+        # in-scatter march: 8 corners x 16 B (packed RGB + extinction) per sample
+        scat_samples = inscatter_samples(wl["n"], wl["M"], wl["dirs"])
+        cands["inscatter"] = 8 * 16 * scat_samples
     per_kernel = {}
     for k, (ms, n) in ktimes.items():
         if n:
             per_kernel[k] = {"avg_ms": ms / n, "launches": n, "total_ms": ms}
     dom = max(cands, key=lambda k: ktimes[k][0])
     dom_avg_s = ktimes[dom][0] / max(ktimes[dom][1], 1) / 1e3
-    achieved = cands[dom] * samples / dom_avg_s / 1e9
+    achieved = cands[dom] / dom_avg_s / 1e9
     traffic = load_traffic(dom, args.workload)
+    n_units = scat_samples if dom == "inscatter" else samples
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_sample": cands[dom], "samples_per_launch": samples}
+                "bytes_per_sample": cands[dom] // n_units, "samples_per_launch": n_units,
+                "avg_ms": round(dom_avg_s * 1e3, 4),
+                "all": {k: {"avg_ms": round(ktimes[k][0] / max(ktimes[k][1], 1), 4),
+                            "achieved_GBs": round(v / (ktimes[k][0] / max(ktimes[k][1], 1) / 1e3) / 1e9, 1)}
+                        for k, v in cands.items() if ktimes[k][1]}}
 
     base = None
     if not args.no_cpu_baseline:

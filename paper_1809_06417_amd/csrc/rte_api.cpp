@@ -196,7 +196,8 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.scat = sizeof(float4) * grids * std::max(M, 1) * std::max(M, 1) * std::max(M, 1);
     s.dirs = sizeof(float4) * kMaxDirs;
     s.dirs_world = 3 * sizeof(double) * kMaxDirs;
-    s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * C * M * M * M : sizeof(float);
+    // per-direction sums plus the slab-pass state (next sample, transmittance)
+    s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * (C + 2) * M * M * M : sizeof(float);
     s.y = sizeof(float) * (size_t)d.n_rays * C;
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
