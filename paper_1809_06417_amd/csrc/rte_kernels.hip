@@ -17,6 +17,7 @@
 //
 // No float atomics anywhere: every sum has a fixed order, so results are
 // bitwise reproducible run to run.
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -430,6 +431,133 @@ __device__ __forceinline__ void scat_sample(const __amdgpu_buffer_rsrc_t &sr, co
     }
 }
 
+// LDS window of the packed volume for the rays of one wave (an 8x8 pixel
+// tile). The tile's rays stay close together, so at each step their samples
+// fall in a few cells: the wave keeps an 8x8x8-node window in LDS, addressed
+// toroidally (node (x, y, z) in slot (x & 7, y & 7, z & 7)), and reads the 8
+// corners of every sample from it. When a sample leaves the window, the wave
+// moves the window so that it starts at the rays' trailing cells along the
+// march direction and loads only the node planes that enter it (one
+// coalesced plane of 64 nodes per load instruction). A sample the window
+// cannot hold (the rays spread over more than 6 cells) reads its corners
+// from memory. The corner values are the same either way.
+constexpr int kWin = 8;
+
+__device__ __forceinline__ int win_slot(int x, int y, int z) { return (x & 7) | ((y & 7) << 3) | ((z & 7) << 6); }
+
+template <int C>
+__device__ __forceinline__ typename Packed<C>::T vload(__amdgpu_buffer_rsrc_t r, int off)
+{
+    if constexpr (C == 3) return bload4(r, off, 0);
+    else return bload2(r, off, 0);
+}
+
+// Load the planes p in [p0, p1) normal to axis `ax` of the window whose other
+// two axes start at (o1, o2); lane l takes node (l & 7, l >> 3) of a plane.
+template <int C>
+__device__ __forceinline__ void win_planes(typename Packed<C>::T *lds, __amdgpu_buffer_rsrc_t vr, int ax, int p0,
+                                           int p1, int o1, int o2, int nx, int ny, int nz, int lane)
+{
+    constexpr int elem = C == 3 ? 16 : 8;
+    const int a1 = lane & 7, a2 = lane >> 3;
+    for (int q = p0; q < p1; ++q) {
+        const int x = ax == 0 ? q : o1 + a1;
+        const int y = ax == 1 ? q : (ax == 0 ? o1 + a1 : o2 + a2);
+        const int z = ax == 2 ? q : o2 + a2;
+        if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
+            lds[win_slot(x, y, z)] = vload<C>(vr, ((z * ny + y) * nx + x) * elem);
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Window origin for one axis: the trailing cell of the wave's samples along
+// the march direction, kept inside the grid.
+__device__ __forceinline__ int win_origin(int mn, int mx, bool forward, int n)
+{
+    int o = forward ? mn : mx - (kWin - 2);
+    o = min(o, n - kWin);
+    return max(o, 0);
+}
+
+template <int C>
+struct VolWindow {
+    typename Packed<C>::T *lds;
+    int ox = 0, oy = 0, oz = 0;
+    bool valid = false;
+    bool fx = true, fy = true, fz = true;  // march direction sign per axis
+
+    // All lanes of the wave call this with their sample's cell; returns
+    // whether the lane's 8 corners are in the window afterwards.
+    __device__ __forceinline__ bool update(bool act, int ix, int iy, int iz, __amdgpu_buffer_rsrc_t vr, int nx,
+                                           int ny, int nz, int lane)
+    {
+        auto inside = [&](int x0, int y0, int z0) {
+            return (unsigned)(ix - x0) <= (unsigned)(kWin - 2) && (unsigned)(iy - y0) <= (unsigned)(kWin - 2) &&
+                   (unsigned)(iz - z0) <= (unsigned)(kWin - 2);
+        };
+        const bool need = act && !(valid && inside(ox, oy, oz));
+        if (__ballot(need) == 0) return act;
+        const int mnx = wave_min(act ? ix : INT_MAX), mxx = wave_max(act ? ix : INT_MIN);
+        const int mny = wave_min(act ? iy : INT_MAX), mxy = wave_max(act ? iy : INT_MIN);
+        const int mnz = wave_min(act ? iz : INT_MAX), mxz = wave_max(act ? iz : INT_MIN);
+        const int nox = __builtin_amdgcn_readfirstlane(win_origin(mnx, mxx, fx, nx));
+        const int noy = __builtin_amdgcn_readfirstlane(win_origin(mny, mxy, fy, ny));
+        const int noz = __builtin_amdgcn_readfirstlane(win_origin(mnz, mxz, fz, nz));
+        const int dx = nox - ox, dy = noy - oy, dz = noz - oz;
+        if (!valid || abs(dx) >= kWin || abs(dy) >= kWin || abs(dz) >= kWin) {
+            win_planes<C>(lds, vr, 2, noz, noz + kWin, nox, noy, nx, ny, nz, lane);
+        } else {
+            // planes entering the window along each axis (edges may load twice)
+            if (dx > 0) win_planes<C>(lds, vr, 0, ox + kWin, nox + kWin, noy, noz, nx, ny, nz, lane);
+            if (dx < 0) win_planes<C>(lds, vr, 0, nox, ox, noy, noz, nx, ny, nz, lane);
+            if (dy > 0) win_planes<C>(lds, vr, 1, oy + kWin, noy + kWin, nox, noz, nx, ny, nz, lane);
+            if (dy < 0) win_planes<C>(lds, vr, 1, noy, oy, nox, noz, nx, ny, nz, lane);
+            if (dz > 0) win_planes<C>(lds, vr, 2, oz + kWin, noz + kWin, nox, noy, nx, ny, nz, lane);
+            if (dz < 0) win_planes<C>(lds, vr, 2, noz, oz, nox, noy, nx, ny, nz, lane);
+        }
+        ox = nox;
+        oy = noy;
+        oz = noz;
+        valid = true;
+        return act && inside(ox, oy, oz);
+    }
+
+    // Trilinear sample from the window (same products and order as
+    // sample_volume_rsrc).
+    __device__ __forceinline__ void sample(int ix, int iy, int iz, const float w[8], float em[C], float &sig) const
+    {
+        sig = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) em[c] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const auto v = lds[win_slot(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1))];
+            if constexpr (C == 3) {
+                em[0] = fmaf(w[c], v.x, em[0]);
+                em[1] = fmaf(w[c], v.y, em[1]);
+                em[2] = fmaf(w[c], v.z, em[2]);
+                sig = fmaf(w[c], v.w, sig);
+            } else {
+                em[0] = fmaf(w[c], v.x, em[0]);
+                sig = fmaf(w[c], v.y, sig);
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------- K1 render
 
 struct RenderArgs {
@@ -473,8 +601,8 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
     const bool in_image = px < a.W && py < a.H;
-    // lanes past the image edge stay for the tile's error butterfly only
-    if (!in_image && !(EPI >= kEpiSart && a.err)) return;
+    // lanes past the image edge stay: they take part in the wave's window
+    // loads and in the tile's error butterfly
     const int HW = a.W * a.H;
     const int pix = in_image ? py * a.W + px : 0;
     const int r = v * HW + pix;
@@ -497,21 +625,46 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     float *gp = nullptr;
     if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
     ScatCorners scc;
-    VolCorners<C> vcc;
-    for (int k = 0; k < K; ++k) {
-        float s, len;
-        segment_of(k, K, A.w, a.ds, s, len);
+    __shared__ typename Packed<C>::T win_lds[4][kWin * kWin * kWin];
+    VolWindow<C> win;
+    win.lds = win_lds[wave];
+    {
+        // march direction of the tile (sum over its rays) per axis
+        float sx = B.x, sy = B.y, sz = B.z;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+        }
+        win.fx = sx >= 0.0f;
+        win.fy = sy >= 0.0f;
+        win.fz = sz >= 0.0f;
+    }
+    // all lanes step together up to the tile's longest march
+    const int Kw = wave_max(K);
+    for (int k = 0; k < Kw; ++k) {
+        const bool act = k < K;
+        float s = 0.0f, len = 0.0f;
+        if (act) segment_of(k, K, A.w, a.ds, s, len);
         const float x = fmaf(s, B.x, A.x), y = fmaf(s, B.y, A.y), z = fmaf(s, B.z, A.z);
         int ix, iy, iz;
         float fx, fy, fz;
         cell_of(x, a.nx, ix, fx);
         cell_of(y, a.ny, iy, fy);
         cell_of(z, a.nz, iz, fz);
+        const bool in_win = win.update(act, ix, iy, iz, vr, a.nx, a.ny, a.nz, lane);
+        if (!act) continue;
         float w[8];
         tri_weights(fx, fy, fz, w);
         float em[C], sig;
-        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sig);
+        if (in_win) {
+            win.sample(ix, iy, iz, w, em, sig);
+        } else {
+            VolCorners<C> vcc;
+            const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
+            sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sig);
+        }
         sig = fmaxf(sig, 0.0f);
         if constexpr (SCAT) {
             int jx, jy, jz;
@@ -540,9 +693,11 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
         T *= e;
     }
     if constexpr (EPI == kEpiImage) {
+        if (in_image) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
-        if (a.exit_T) a.exit_T[r] = T;
+            for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
+            if (a.exit_T) a.exit_T[r] = T;
+        }
     } else if constexpr (EPI == kEpiSart || EPI == kEpiMlem || EPI == kEpiPaper) {
         const float m = !in_image ? 0.0f : (a.mask ? a.mask[r] : 1.0f);
         const float inv = Rsum > 0.0f ? 1.0f / Rsum : 0.0f;
