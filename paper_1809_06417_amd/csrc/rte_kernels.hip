@@ -802,13 +802,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-    if (px >= a.W || py >= a.H) return;
+    // lanes past the image edge or missing the box stay for the window loads
+    const bool in_image = px < a.W && py < a.H;
     const int HW = a.W * a.H;
-    const int pix = py * a.W + px;
+    const int pix = in_image ? py * a.W + px : 0;
     const int r = v * HW + pix;
     const float4 A = a.rayA[r], B = a.rayB[r];
-    const int K = __float_as_int(B.w);
-    if (K == 0) return;
+    const int K = in_image ? __float_as_int(B.w) : 0;
     const int nx = a.nx, nxy = a.nx * a.ny;
     constexpr int elem = C == 3 ? 16 : 8;
     const __amdgpu_buffer_rsrc_t vr = make_rsrc(a.vol, (int64_t)nxy * a.nz * elem);
@@ -829,21 +829,47 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     float *gp = a.g + a.tile_off[tile] + lane;
     float *qp = a.q + a.tile_off[tile] + lane;
     ScatCorners scc;
-    VolCorners<C> vcc;
-    for (int k = K - 1; k >= 0; --k) {
-        float s, len;
-        segment_of(k, K, A.w, a.ds, s, len);
+    __shared__ typename Packed<C>::T win_lds[4][kWin * kWin * kWin];
+    VolWindow<C> win;
+    win.lds = win_lds[wave];
+    {
+        // the march runs back to front: the window trails along -direction
+        float sx = B.x, sy = B.y, sz = B.z;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            sz += __shfl_xor(sz, off, 64);
+        }
+        win.fx = sx < 0.0f;
+        win.fy = sy < 0.0f;
+        win.fz = sz < 0.0f;
+    }
+    // all lanes step together; step j takes sample K - 1 - j of each ray
+    const int Kw = wave_max(K);
+    for (int j = 0; j < Kw; ++j) {
+        const int k = K - 1 - j;
+        const bool act = k >= 0;
+        float s = 0.0f, len = 0.0f;
+        if (act) segment_of(k, K, A.w, a.ds, s, len);
         const float x = fmaf(s, B.x, A.x), yy = fmaf(s, B.y, A.y), z = fmaf(s, B.z, A.z);
         int ix, iy, iz;
         float fx, fy, fz;
         cell_of(x, a.nx, ix, fx);
         cell_of(yy, a.ny, iy, fy);
         cell_of(z, a.nz, iz, fz);
+        const bool in_win = win.update(act, ix, iy, iz, vr, a.nx, a.ny, a.nz, lane);
+        if (!act) continue;
         float w[8];
         tri_weights(fx, fy, fz, w);
         float em[C], sraw;
-        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sraw);
+        if (in_win) {
+            win.sample(ix, iy, iz, w, em, sraw);
+        } else {
+            VolCorners<C> vcc;
+            const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
+            sample_volume_rsrc<C>(vr, coff, base * elem, w, vcc, em, sraw);
+        }
         const float sig = fmaxf(sraw, 0.0f);
         float S[3] = {0.f, 0.f, 0.f};
         if constexpr (SCAT) {
