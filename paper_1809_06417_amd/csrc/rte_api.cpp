@@ -198,7 +198,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.dirs_world = 3 * sizeof(double) * kMaxDirs;
     // per-direction sums plus the slab-pass state (next sample, transmittance)
     s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * (C + 2) * M * M * M : sizeof(float);
-    s.y = sizeof(float) * (size_t)d.n_rays * C;
+    s.y = sizeof(float) * (size_t)d.n_rays * (C == 3 ? 4 : 1);  // per ray: float4 (RGB, pad) or float
     s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
@@ -655,8 +655,8 @@ int rte_render_backward(rte_plan *plan, const float *emission, const float *exti
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
     if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
     RTE_LAUNCH(plan, RTE_KERNEL_ADJOINT, s, rte::launch_adjoint_march(plan, scat, exit_transmittance, grad_images, s));
-    RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
-               rte::launch_gather(plan, C, rte::kGatherGrad, grad_images, 0.f, 0.f, 0.f, s));
+    const float *dI = rte::launch_pack_residual(plan, grad_images, s);
+    RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_gather(plan, C, rte::kGatherGrad, dI, 0.f, 0.f, 0.f, s));
     RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                rte::launch_update(plan, C, C + 1, rte::kUpdGrad, 0.f, 0, grad_emission, nullptr, 0, 0, s,
                                   grad_extinction));
@@ -690,16 +690,15 @@ int rte_backproject(rte_plan *plan, const float *extinction, const float *residu
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
     const int C = plan->params.channels;
+    const float *y = rte::launch_pack_residual(plan, residual, s);
     if (mode == RTE_BP_ADJOINT) {
         RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, nullptr, extinction, C, s));
         RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
-                   rte::launch_gather(plan, C, rte::kGatherAdjoint, residual, 0.f, 0.f, 0.f, s));
+        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_gather(plan, C, rte::kGatherAdjoint, y, 0.f, 0.f, 0.f, s));
     } else {
         RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
-                   rte::launch_gather(plan, C, rte::kGatherPaper, residual, params->alpha_l,
-                                      params->alpha_d, params->tau, s));
+                   rte::launch_gather(plan, C, rte::kGatherPaper, y, params->alpha_l, params->alpha_d, params->tau, s));
     }
     RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                rte::launch_update(plan, C, C, rte::kUpdDelta, 0.f, 0, delta, nullptr, 0, 0, s));

@@ -139,6 +139,9 @@ hipError_t launch_pack(const rte_plan *p, const float *emission, const float *ex
 // launches. marks: NULL or 6 events recorded around the three launches.
 hipError_t launch_step_batch(rte_plan *const *plans, int n, hipStream_t s, hipEvent_t *marks = nullptr);
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s);
+// Residuals in the gather's per-ray layout: packs planar [V][3][H][W] into
+// the plan's residual buffer and returns it (one channel: returns planar).
+const float *launch_pack_residual(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,

@@ -702,17 +702,22 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
         const float m = !in_image ? 0.0f : (a.mask ? a.mask[r] : 1.0f);
         const float inv = Rsum > 0.0f ? 1.0f / Rsum : 0.0f;
         float r2 = 0.0f;
+        float yo[C];
 #pragma unroll
-        for (int c = 0; c < C && in_image; ++c) {
-            const int i = (v * C + c) * HW + pix;
-            const float F = a.frames[(v * a.fC + a.fc0 + c) * HW + pix];
+        for (int c = 0; c < C; ++c) {
+            const float F = in_image ? a.frames[(v * a.fC + a.fc0 + c) * HW + pix] : 0.0f;
             const float It = fmaf(T, a.background, I[c]);
             float yv;
             if constexpr (EPI == kEpiSart) yv = (F - It) * inv;
             else if constexpr (EPI == kEpiMlem) yv = It > 0.0f ? F / It : 1.0f;
             else yv = F - It;
-            a.out[i] = m != 0.0f ? yv : 0.0f;
-            r2 = fmaf(F - It, F - It, r2);
+            yo[c] = m != 0.0f ? yv : 0.0f;
+            if (in_image) r2 = fmaf(F - It, F - It, r2);
+        }
+        // residuals per ray, one 16-byte store for three channels
+        if (in_image) {
+            if constexpr (C == 3) reinterpret_cast<float4 *>(a.out)[r] = make_float4(yo[0], yo[1], yo[2], 0.0f);
+            else a.out[r] = yo[0];
         }
         if (a.err) {
             // fixed-order butterfly over the tile's 64 rays; lane 0 stores it
@@ -1122,7 +1127,7 @@ struct GatherArgs {
     const uint64_t *tile_off;
     const float *g;
     const float *q;        // second per-sample buffer (gradient mode)
-    const float *y;        // [V][C][H][W]
+    const float *y;        // residual per ray [V][H][W]: float4 (RGB, pad) for 3 channels, float for 1
     const ViewProj *proj;
     float *part;           // [8][acc][cells]
     int V, W, H, tiles_x, tiles_per_view;
@@ -1239,8 +1244,14 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                 if (k_lo > k_hi) continue;
                 float yv[C];
                 if constexpr (MODE != kGatherCols && MODE != kGatherHull) {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) yv[c] = a.y[(v * C + c) * HW + pix];
+                    if constexpr (C == 3) {
+                        const float4 y4 = reinterpret_cast<const float4 *>(a.y)[r];
+                        yv[0] = y4.x;
+                        yv[1] = y4.y;
+                        yv[2] = y4.z;
+                    } else {
+                        yv[0] = a.y[r];
+                    }
                 }
                 const int tile = v * a.tiles_per_view + (py >> 3) * a.tiles_x + (px >> 3);
                 const float *gp = a.g + a.tile_off[tile] + ((py & 7) * 8 + (px & 7));
@@ -1626,6 +1637,26 @@ hipError_t launch_pack(const rte_plan *p, const float *emission, const float *ex
     else
         hipLaunchKernelGGL(pack_kernel<1>, dim3(blocks_for(p->n_nodes)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+// Planar residuals [V][3][H][W] -> one float4 (RGB, 0) per ray, the layout
+// the gather reads.
+__global__ __launch_bounds__(kBlock) void pack_residual_kernel(const float *planar, float4 *out, int V, int HW)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= (int64_t)V * HW) return;
+    const int64_t v = r / HW, pix = r - v * HW;
+    const float *p = planar + v * 3 * HW + pix;
+    out[r] = make_float4(p[0], p[HW], p[2 * HW], 0.0f);
+}
+
+const float *launch_pack_residual(const rte_plan *p, const float *planar, hipStream_t s)
+{
+    if (p->params.channels != 3) return planar;  // one channel: the layouts agree
+    const int64_t n = (int64_t)p->V * p->W * p->H;
+    hipLaunchKernelGGL(pack_residual_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, planar,
+                       reinterpret_cast<float4 *>(p->d_y), p->V, p->W * p->H);
+    return p->d_y;
 }
 
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s)
