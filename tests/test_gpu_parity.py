@@ -398,3 +398,34 @@ def test_camera_inside_the_volume():
         d = host(p.backproject(dev(sig), dev(y)))
     assert render_rel(img, ref) <= RENDER_REL
     assert rel_max(d, bref) <= BACKPROJ_REL
+
+
+@pytest.mark.parametrize("C", [1, 3])
+def test_spread_out_tile_uses_the_memory_fallback(C):
+    """8x8 images with a 100-degree field of view over a 40^3 grid: the 64 rays
+    of the single tile spread over far more than the render's 8^3-node LDS
+    window, so most samples read their corners from memory and the window
+    is moved on almost every step. Render (with in-scattering and a
+    background), weights and the back-projection must still match the
+    oracle, and a short reconstruction too."""
+    g = synth.Grid(40, 40, 40)
+    rig = synth.ring_rig(3, 8, 8, radius=1.2, fov_y_deg=100.0, elevation_jitter_deg=20, seed=9)
+    em, sig = blob_volume(g, C, 12, n_blobs=5)
+    S = oracle.inscatter(g, as64(em), as64(sig), s_res=6, n_dirs=8) if C == 3 else None
+    kw = dict(step_vox=STEP, albedo=0.3 if C == 3 else 0.0, background=0.1, inscatter=S)
+    ref = oracle.render(g, rig, as64(em), as64(sig), **kw)
+    y = f32(np.random.default_rng(2).normal(size=ref.shape))
+    bref = oracle.backproject_adjoint(g, rig, as64(sig), as64(y), step_vox=STEP)
+    F = f32(ref)
+    xref = oracle.reconstruct(g, rig, as64(F), as64(sig), np.zeros(em.shape), 3, step_vox=STEP,
+                              albedo=kw["albedo"], background=0.1, s_res=6, n_dirs=8)
+    say("spread-out tile", C)
+    with rte().Plan(g, rig, channels=C, step_vox=STEP, albedo=kw["albedo"], background=0.1,
+                    scatter_res=6 if C == 3 else 0, scatter_dirs=8) as p:
+        img = host(p.render(dev(em), dev(sig), None if S is None else dev(S)))
+        d = host(p.backproject(dev(sig), dev(y)))
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 3))
+    assert render_rel(img, ref) <= RENDER_REL
+    assert rel_max(d, bref) <= BACKPROJ_REL
+    for ch in range(C):
+        assert rel_rms(x[ch], xref[ch]) <= VOLUME_RMS
