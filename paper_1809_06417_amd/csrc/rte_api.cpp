@@ -189,7 +189,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.tnear = sizeof(float) * d.n_rays;
     s.tiles = (2 * sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
     s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
-    s.q = grads ? s.g : 0;
+    s.q = grads ? 2 * s.g : 0;  // (g_k, q_k) pairs of the adjoint march
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
     // one in-scatter grid per view for an anisotropic phase function
     const size_t grids = (M && params->phase_g != 0.0f) ? (size_t)d.V : 1;

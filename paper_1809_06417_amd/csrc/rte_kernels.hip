@@ -779,7 +779,7 @@ struct GradArgs {
     int scat_vstride;     // as in RenderArgs
     const float *exit_T;  // [V][H][W]
     const float *dI;      // dL/dI [V][C][H][W]
-    float *g, *q;         // per-sample outputs, [tile][k][lane]
+    float2 *gq;           // per-sample outputs (g_k, q_k), [tile][k][lane]
     int W, H, tiles_x, tiles_per_view;
     int nx, ny, nz, M;
     float ds, albedo, background;
@@ -831,8 +831,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
         y[c] = a.dI[(v * C + c) * HW + pix];
         R[c] = T * a.background;
     }
-    float *gp = a.g + a.tile_off[tile] + lane;
-    float *qp = a.q + a.tile_off[tile] + lane;
+    float2 *gqp = a.gq + a.tile_off[tile] + lane;
     ScatCorners scc;
     __shared__ typename Packed<C>::T win_lds[4][kWin * kWin * kWin];
     VolWindow<C> win;
@@ -904,8 +903,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
             qk = fmaf(y[c], fmaf(-len, R[c], dc), qk);
             R[c] = fmaf(gk, em[c], R[c]);
         }
-        gp[k * kTileRays] = gk;
-        qp[k * kTileRays] = sraw >= 0.0f ? qk : 0.0f;
+        gqp[k * kTileRays] = make_float2(gk, sraw >= 0.0f ? qk : 0.0f);
     }
 }
 
@@ -1126,7 +1124,7 @@ struct GatherArgs {
     const float4 *rayA, *rayB;
     const uint64_t *tile_off;
     const float *g;
-    const float *q;        // second per-sample buffer (gradient mode)
+    const float *q;        // gradient mode: per-sample (g_k, q_k) pairs, float2 [tile][k][lane]
     const float *y;        // residual per ray [V][H][W]: float4 (RGB, pad) for 3 channels, float for 1
     const ViewProj *proj;
     float *part;           // [8][acc][cells]
@@ -1283,7 +1281,14 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                             for (int q = 0; q < C; ++q) acc[c][q] = fmaf(amp, yv[q], acc[c][q]);
                         }
                     } else {
-                        const float gk = gp[k * kTileRays];
+                        float gk, qk = 0.0f;
+                        if constexpr (MODE == kGatherGrad) {
+                            const float2 gq = reinterpret_cast<const float2 *>(a.q)[(gp - a.g) + k * kTileRays];
+                            gk = gq.x;
+                            qk = gq.y;
+                        } else {
+                            gk = gp[k * kTileRays];
+                        }
                         float w[8];
                         tri_weights(fx, fy, fz, w);
                         if constexpr (MODE == kGatherCols) {
@@ -1291,7 +1296,6 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
 #pragma unroll
                             for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gm, w[c], acc[c][0]);
                         } else if constexpr (MODE == kGatherGrad) {
-                            const float qk = a.q[(gp - a.g) + k * kTileRays];
                             float gy[C];
 #pragma unroll
                             for (int qq = 0; qq < C; ++qq) gy[qq] = gk * yv[qq];
@@ -1850,8 +1854,7 @@ hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float
     a.scat_vstride = scat_view_stride(p);
     a.exit_T = exit_T;
     a.dI = dI;
-    a.g = p->d_g;
-    a.q = p->d_q;
+    a.gq = reinterpret_cast<float2 *>(p->d_q);
     a.W = p->W;
     a.H = p->H;
     a.tiles_x = p->tiles_x;
