@@ -204,32 +204,6 @@ __device__ __forceinline__ float sample_gain(uint32_t seed_lo, uint32_t seed_hi,
 }
 
 
-// Trilinear sample of the packed volume: emission channels and extinction.
-template <int C>
-__device__ __forceinline__ void sample_volume(const typename Packed<C>::T *__restrict__ vol, int nx,
-                                              int nxy, int ix, int iy, int iz, const float w[8],
-                                              float em[C], float &sig)
-{
-    const int base = (iz * nxy + iy * nx) + ix;
-    const int off[8] = {0, 1, nx, nx + 1, nxy, nxy + 1, nxy + nx, nxy + nx + 1};
-    sig = 0.0f;
-#pragma unroll
-    for (int c = 0; c < C; ++c) em[c] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const auto v = vol[base + off[c]];
-        if constexpr (C == 3) {
-            em[0] = fmaf(w[c], v.x, em[0]);
-            em[1] = fmaf(w[c], v.y, em[1]);
-            em[2] = fmaf(w[c], v.z, em[2]);
-            sig = fmaf(w[c], v.w, sig);
-        } else {
-            em[0] = fmaf(w[c], v.x, em[0]);
-            sig = fmaf(w[c], v.y, sig);
-        }
-    }
-}
-
 // ------------------------------------------------------------- K4 ray table
 
 struct RayArgs {
