@@ -1,0 +1,81 @@
+"""Randomised GPU parity (seeded, hypothesis-driven): small grids of any
+shape (including fewer than 8 key points per axis), boxes off the unit cube,
+1-3 cameras anywhere outside or inside the box with random orientation and
+field of view, ragged images of 1-23 pixels per side, one or three channels.
+Render and adjoint back-projection through the C ABI against the FP64
+oracle at every generated case."""
+import numpy as np
+import pytest
+
+hypothesis = pytest.importorskip("hypothesis")
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from gpu_util import BACKPROJ_REL, RENDER_REL, as64, dev, f32, host, rel_max, render_rel, say  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def rte():
+    from paper_1809_06417_amd import rte as _rte
+    return _rte
+
+
+@st.composite
+def cases(draw):
+    nx, ny, nz = (draw(st.integers(2, 14)) for _ in range(3))
+    lo = np.array([draw(st.floats(-1.0, 1.0)) for _ in range(3)])
+    ext = np.array([draw(st.floats(0.3, 2.0)) for _ in range(3)])
+    V = draw(st.integers(1, 3))
+    W, H = draw(st.integers(1, 23)), draw(st.integers(1, 23))
+    C = draw(st.sampled_from([1, 3]))
+    seed = draw(st.integers(0, 2**31 - 1))
+    inside = draw(st.booleans())
+    return nx, ny, nz, lo, ext, V, W, H, C, seed, inside
+
+
+def build(nx, ny, nz, lo, ext, V, W, H, C, seed, inside):
+    rng = np.random.default_rng(seed)
+    g = synth.Grid(nx, ny, nz, lo=tuple(lo), hi=tuple(lo + ext))
+    centre = lo + ext / 2
+    Rs, ts = [], []
+    for v in range(V):
+        if inside and v == 0:
+            eye = lo + ext * rng.uniform(0.2, 0.8, 3)
+        else:
+            d = rng.normal(size=3)
+            eye = centre + d / np.linalg.norm(d) * np.linalg.norm(ext) * rng.uniform(0.8, 3.0)
+        target = centre + ext * rng.uniform(-0.3, 0.3, 3)
+        up = np.array([0.0, 0.0, 1.0]) if abs((target - eye)[2]) < 0.9 * np.linalg.norm(target - eye) \
+            else np.array([1.0, 0.0, 0.0])
+        R, t = synth._look_at(eye, target, up)
+        Rs.append(R)
+        ts.append(t)
+    fov = rng.uniform(20.0, 100.0)
+    f = (H / 2.0) / np.tan(np.radians(fov) / 2.0)
+    rig = synth.Rig(np.full(V, f), np.full(V, f * rng.uniform(0.8, 1.25)), np.full(V, W / 2.0),
+                    np.full(V, H / 2.0), np.array(Rs), np.array(ts), W, H)
+    em = f32(rng.uniform(0.0, 1.0, size=(C, nz, ny, nx)))
+    sig = f32(rng.uniform(0.0, 3.0, size=(nz, ny, nx)) / np.min(ext))
+    return g, rig, em, sig
+
+
+@settings(max_examples=40, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(cases())
+def test_random_render_and_backprojection_match_oracle(case):
+    g, rig, em, sig = build(*case)
+    C = em.shape[0]
+    ref = oracle.render(g, rig, as64(em), as64(sig), step_vox=0.5, background=0.05)
+    y = f32(np.random.default_rng(case[9] + 1).normal(size=ref.shape))
+    bref = oracle.backproject_adjoint(g, rig, as64(sig), as64(y), step_vox=0.5)
+    say("random case", case[:3], "views", case[5], "image", case[6:8], "C", C, "seed", case[9], "inside", case[10])
+    with rte().Plan(g, rig, channels=C, step_vox=0.5, background=0.05) as p:
+        img = host(p.render(dev(em), dev(sig)))
+        d = host(p.backproject(dev(sig), dev(y)))
+    assert render_rel(img, ref) <= RENDER_REL
+    if np.abs(bref).max() > 0:
+        assert rel_max(d, bref) <= BACKPROJ_REL
+    else:
+        assert np.abs(d).max() == 0.0
