@@ -187,7 +187,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.proj = sizeof(rte::ViewProj) * d.V;
     s.rays = 2 * sizeof(float4) * d.n_rays;
     s.tnear = sizeof(float) * d.n_rays;
-    s.tiles = (2 * sizeof(int32_t) + sizeof(uint64_t)) * d.n_tiles;
+    s.tiles = 3 * sizeof(int32_t) * d.n_tiles;
     s.g = sizeof(float) * std::max<uint64_t>(g_floats, 1);
     s.q = grads ? 2 * s.g : 0;  // (g_k, q_k) pairs of the adjoint march
     s.vol = (C == 3 ? 16 : 8) * (size_t)d.n_nodes;
@@ -428,7 +428,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         (rc = dev_alloc(&p->d_rayA, sz.rays / 2, acc)) || (rc = dev_alloc(&p->d_rayB, sz.rays / 2, acc)) ||
         (rc = dev_alloc(&p->d_tnear, sz.tnear, acc)) ||
         (rc = dev_alloc(&p->d_tile_kmax, sizeof(int32_t) * d.n_tiles, acc)) ||
-        (rc = dev_alloc(&p->d_tile_off, sizeof(uint64_t) * d.n_tiles, acc)))
+        (rc = dev_alloc(&p->d_tile_off, sizeof(uint32_t) * d.n_tiles, acc)))
         return bail(rc);
     std::vector<rte::ViewProj> proj(d.V);
     for (int v = 0; v < d.V; ++v) proj[v] = view_projection(grid, cams[v], d.h);
@@ -445,14 +445,17 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     if (hipMemcpyAsync(kmax.data(), p->d_tile_kmax, sizeof(int32_t) * d.n_tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return bail(fail(RTE_ERR_HIP, "ray table readback failed"));
-    std::vector<uint64_t> off(d.n_tiles);
+    std::vector<uint32_t> off(d.n_tiles);
     uint64_t g = 0;
     for (int t = 0; t < d.n_tiles; ++t) {
         if (kmax[t] > host_kmax[t] + 1)
             return bail(fail(RTE_ERR_HIP, "device ray table disagrees with the host bound at tile %d", t));
-        off[t] = g;
+        off[t] = (uint32_t)g;
         g += (uint64_t)kmax[t] * rte::kTileRays;
     }
+    if (g > 0xFFFFFFFFull)
+        return bail(fail(RTE_ERR_UNSUPPORTED, "%llu per-sample slots exceed the 2^32 a plan addresses; use fewer views "
+                                              "or a coarser step", (unsigned long long)g));
     p->g_floats = g;
     // launch order of the render: tiles that hold samples, longest march first
     // (stable, so equal tiles keep their spatial order); tiles without
@@ -466,7 +469,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         if (kmax[t] == 0) order.push_back(t);
     if ((rc = dev_alloc(&p->d_tile_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1), acc)))
         return bail(rc);
-    if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint64_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint32_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess ||
         (!order.empty() && hipMemcpyAsync(p->d_tile_order, order.data(), sizeof(int32_t) * order.size(),
                                           hipMemcpyHostToDevice, s) != hipSuccess))
         return bail(fail(RTE_ERR_HIP, "tile tables upload failed"));

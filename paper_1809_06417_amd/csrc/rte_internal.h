@@ -79,7 +79,7 @@ struct rte_plan {
     float4 *d_rayB = nullptr;       // direction (voxel units per world unit) xyz, K (int bits) w
     float *d_tnear = nullptr;       // entry distance (export only)
     int32_t *d_tile_kmax = nullptr;
-    uint64_t *d_tile_off = nullptr;
+    uint32_t *d_tile_off = nullptr;  // per tile: first slot in d_g (plans keep < 2^32 slots)
     int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
     int n_active_tiles = 0;
     float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]

@@ -536,7 +536,7 @@ struct VolWindow {
 
 struct RenderArgs {
     const float4 *rayA, *rayB;
-    const uint64_t *tile_off;
+    const uint32_t *tile_off;  // first slot of each tile in the per-sample buffers
     const int32_t *tile_order;  // tiles with samples (heaviest first), then empty tiles
     int n_launch;               // leading entries of tile_order this launch covers
     const float *vol;
@@ -745,7 +745,7 @@ __device__ __forceinline__ float dphi_f(float x, float e)
 
 struct GradArgs {
     const float4 *rayA, *rayB;
-    const uint64_t *tile_off;
+    const uint32_t *tile_off;  // first slot of each tile in the per-sample buffers
     const int32_t *tile_order;
     int n_launch;
     const float *vol;
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_kernel(ScatArgs
 
 struct GatherArgs {
     const float4 *rayA, *rayB;
-    const uint64_t *tile_off;
+    const uint32_t *tile_off;  // first slot of each tile in the per-sample buffers
     const float *g;
     const float *q;        // gradient mode: per-sample (g_k, q_k) pairs, float2 [tile][k][lane]
     const float *y;        // residual per ray [V][H][W]: float4 (RGB, pad) for 3 channels, float for 1

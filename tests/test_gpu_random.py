@@ -61,7 +61,7 @@ def build(nx, ny, nz, lo, ext, V, W, H, C, seed, inside):
     return g, rig, em, sig
 
 
-@settings(max_examples=40, deadline=None, derandomize=True,
+@settings(max_examples=120, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(cases())
 def test_random_render_and_backprojection_match_oracle(case):
