@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="colour", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=4)
+    ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU baseline sample (one FP64 iteration)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--hbm-budget-gib", type=int, default=64, help="serve: workspace budget for resident plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
