@@ -38,7 +38,7 @@ class _ReconParams(ct.Structure):
                 ("alpha_l", ct.c_double), ("alpha_d", ct.c_double), ("tau", ct.c_double),
                 ("g_sigma", ct.c_double), ("seed", ct.c_uint64), ("use_mask", ct.c_int32),
                 ("flame_threshold", ct.c_double), ("use_hull", ct.c_int32),
-                ("outside_value", ct.c_double), ("stop_tol", ct.c_double)]
+                ("outside_value", ct.c_double), ("stop_tol", ct.c_double), ("subsets", ct.c_int32)]
 
 
 class _TempParams(ct.Structure):
@@ -352,9 +352,11 @@ def visual_hull(grid, rig, mask, *, step_vox=0.5):
 def reconstruct_ext(grid, rig, frames, extinction, emission0, iters, *, step_vox=0.5, albedo=0.0,
                     background=0.0, s_res=32, n_dirs=32, s_step=0.5, phase_g=0.0, mode="sart", lam=1.0,
                     clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, g_sigma=0.0, seed=0,
-                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0):
+                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0, subsets=1):
     """Reconstruction with the paper's variants (flame mask, visual hull, gains
-    G(s), stop rule). Returns (emission, per-iteration image RMS, updates made)."""
+    G(s), stop rule) and ordered subsets of views. Returns (emission,
+    per-iteration image RMS, updates made); with subsets > 1 the RMS is not
+    computed (zeros) and the update count is in iterations."""
     F = _f64(frames)
     em = np.array(emission0, dtype=np.float64, order="C", copy=True)
     rp = _ReconParams()
@@ -365,6 +367,7 @@ def reconstruct_ext(grid, rig, frames, extinction, emission0, iters, *, step_vox
     rp.use_mask = 0 if flame_threshold is None else 1
     rp.flame_threshold = 0.0 if flame_threshold is None else float(flame_threshold)
     rp.use_hull, rp.outside_value, rp.stop_tol = 1 if hull else 0, float(outside_value), float(stop_tol)
+    rp.subsets = int(subsets)
     res = np.zeros(max(iters, 1))
     done = ct.c_int32()
     _check(lib().orc_reconstruct_ext(ct.byref(_grid(grid)), _cams(rig), rig.n_views, em.shape[0],

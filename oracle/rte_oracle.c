@@ -940,6 +940,7 @@ typedef struct {
     int32_t use_hull;        /* reconstruct key points inside the visual hull only */
     double outside_value;    /* value given to key points outside the hull */
     double stop_tol;         /* > 0: stop when successive image errors differ by less */
+    int32_t subsets;         /* > 1: ordered subsets of views (view v in subset v mod subsets) */
 } orc_recon_params;
 
 /* Paper-mode adjustment with per-sample gains and a ray mask (Eq. 10-12):
@@ -1005,11 +1006,148 @@ static int backproject_paper_ext(const orc_grid *g, const orc_camera *cams, int3
  *    the update of iteration it; stop before updating when it >= 1 and
  *    |E_{it-1} - E_it| < stop_tol.
  * iters_done receives the number of updates made; resid_out[it] = E_it. */
+/* Ordered subsets (the classic per-view form of SART, OS-EM): the views are
+ * split into n subsets (view v in subset v mod n) and every iteration
+ * updates the volume once per subset in order, each update being the
+ * simultaneous step of the chosen rule restricted to that subset's rays:
+ * its own row sums and its own column sums C_j^s = (A_s^T 1)_j. The
+ * in-scatter grid is recomputed at the start of each iteration and held
+ * fixed over its subsets. Flame mask and visual hull apply as in
+ * orc_reconstruct_ext; the gains G(s) and the stop rule are not combined
+ * with subsets. */
+static int reconstruct_subsets(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
+                               double albedo, double background, int32_t s_res, int32_t n_dirs, double s_step,
+                               double phase_g, const double *frames, const double *sig, double *em_io,
+                               int32_t iters, const orc_recon_params *rp, int32_t *iters_done)
+{
+    const int ns = rp->subsets;
+    if (ns > V || rp->stop_tol > 0.0 || rp->g_sigma != 0.0) return -1;
+    long N = grid_nodes(g);
+    long HW = (long)cams[0].width * cams[0].height;
+    long M3 = (long)s_res * s_res * s_res;
+    int vmax = (V + ns - 1) / ns;
+    orc_camera *sc = (orc_camera *)malloc(sizeof(orc_camera) * vmax);
+    double *F = (double *)malloc(sizeof(double) * vmax * C * HW);
+    double *img = (double *)malloc(sizeof(double) * vmax * C * HW);
+    double *y = (double *)malloc(sizeof(double) * vmax * C * HW);
+    double *rows = (double *)malloc(sizeof(double) * vmax * HW);
+    double *mask_all = (double *)malloc(sizeof(double) * V * HW);
+    double *mask = (double *)malloc(sizeof(double) * vmax * HW);
+    double *cols = (double *)malloc(sizeof(double) * ns * N);
+    double *ones_n = (double *)malloc(sizeof(double) * N);
+    double *delta = (double *)malloc(sizeof(double) * C * N);
+    int32_t *inside = (int32_t *)malloc(sizeof(int32_t) * N);
+    long n_grids = phase_g != 0.0 ? V : 1;
+    double *S = (albedo != 0.0 && s_res >= 2) ? (double *)malloc(sizeof(double) * n_grids * C * M3) : NULL;
+    double *Ss = (albedo != 0.0 && s_res >= 2 && phase_g != 0.0) ? (double *)malloc(sizeof(double) * vmax * C * M3)
+                                                                  : NULL;
+    int rc = 0, done = 0;
+    if (!sc || !F || !img || !y || !rows || !mask_all || !mask || !cols || !ones_n || !delta || !inside ||
+        (albedo != 0.0 && s_res >= 2 && !S) || (albedo != 0.0 && s_res >= 2 && phase_g != 0.0 && !Ss)) {
+        rc = -2;
+        goto done;
+    }
+    if (rp->use_mask) orc_flame_mask(frames, V, C, HW, rp->flame_threshold, mask_all);
+    else for (long i = 0; i < V * HW; ++i) mask_all[i] = 1.0;
+    if (rp->use_hull) {
+        rc = orc_visual_hull(g, cams, V, step_vox, mask_all, inside);
+        if (rc) goto done;
+        for (int ch = 0; ch < C; ++ch)
+            for (long j = 0; j < N; ++j)
+                if (!inside[j]) em_io[(long)ch * N + j] = rp->outside_value;
+    } else {
+        for (long j = 0; j < N; ++j) inside[j] = 1;
+    }
+    for (long i = 0; i < N; ++i) ones_n[i] = 1.0;
+    /* gather subset s: its cameras, frames and mask rows; returns its view count */
+#define TAKE_SUBSET(s_)                                                                            \
+    int vs = 0;                                                                                    \
+    for (int v = (s_); v < V; v += ns, ++vs) {                                                     \
+        sc[vs] = cams[v];                                                                          \
+        memcpy(F + (long)vs * C * HW, frames + (long)v * C * HW, sizeof(double) * C * HW);         \
+        memcpy(mask + (long)vs * HW, mask_all + (long)v * HW, sizeof(double) * HW);                \
+    }
+    if (rp->mode == 0 || rp->mode == 2)
+        for (int s = 0; s < ns; ++s) {
+            TAKE_SUBSET(s)
+            rc = orc_backproject_adjoint(g, sc, vs, 1, step_vox, sig, mask, cols + (long)s * N);
+            if (rc) goto done;
+        }
+    for (int it = 0; it < iters; ++it) {
+        if (S) {
+            rc = phase_g != 0.0
+                     ? orc_inscatter_phase(g, cams, V, C, em_io, sig, s_res, n_dirs, s_step, phase_g, S)
+                     : orc_inscatter(g, C, em_io, sig, s_res, n_dirs, s_step, S);
+            if (rc) goto done;
+        }
+        for (int s = 0; s < ns; ++s) {
+            TAKE_SUBSET(s)
+            const double *Sv = S;
+            if (S && phase_g != 0.0) {
+                for (int k = 0, v = s; v < V; v += ns, ++k)
+                    memcpy(Ss + (long)k * C * M3, S + (long)v * C * M3, sizeof(double) * C * M3);
+                Sv = Ss;
+            }
+            rc = orc_render(g, sc, vs, C, step_vox, albedo, background, em_io, sig, s_res, Sv, phase_g != 0.0,
+                            img, NULL);
+            if (rc) goto done;
+            if (rp->mode == 0 || rp->mode == 2) {
+                rc = orc_render(g, sc, vs, 1, step_vox, 0.0, 0.0, ones_n, sig, 0, NULL, 0, rows, NULL);
+                if (rc) goto done;
+            }
+            for (int v = 0; v < vs; ++v)
+                for (int ch = 0; ch < C; ++ch)
+                    for (long p = 0; p < HW; ++p) {
+                        long i = ((long)v * C + ch) * HW + p;
+                        double m = mask[(long)v * HW + p];
+                        if (rp->mode == 0) {
+                            double R = rows[(long)v * HW + p];
+                            y[i] = (m != 0.0 && R > 0.0) ? (F[i] - img[i]) / R : 0.0;
+                        } else if (rp->mode == 2) {
+                            y[i] = m != 0.0 ? (img[i] > 0.0 ? F[i] / img[i] : 1.0) : 0.0;
+                        } else {
+                            y[i] = m != 0.0 ? F[i] - img[i] : 0.0;
+                        }
+                    }
+            if (rp->mode == 1)
+                rc = orc_backproject_paper(g, sc, vs, C, step_vox, rp->alpha_l, rp->alpha_d, rp->tau, y, delta);
+            else
+                rc = orc_backproject_adjoint(g, sc, vs, C, step_vox, sig, y, delta);
+            if (rc) goto done;
+            const double *cs = cols + (long)s * N;
+            for (int ch = 0; ch < C; ++ch)
+                for (long j = 0; j < N; ++j) {
+                    if (!inside[j]) continue;
+                    double e = em_io[(long)ch * N + j];
+                    if (rp->mode == 1) {
+                        e += delta[(long)ch * N + j];
+                    } else {
+                        if (!(cs[j] > 0.0)) continue;
+                        if (rp->mode == 0) e += rp->lambda * delta[(long)ch * N + j] / cs[j];
+                        else e *= 1.0 + rp->lambda * (delta[(long)ch * N + j] / cs[j] - 1.0);
+                    }
+                    if (rp->clamp_nonneg && e < 0.0) e = 0.0;
+                    em_io[(long)ch * N + j] = e;
+                }
+        }
+        ++done;
+    }
+#undef TAKE_SUBSET
+done:
+    if (iters_done) *iters_done = done;
+    free(sc); free(F); free(img); free(y); free(rows); free(mask_all); free(mask); free(cols); free(ones_n);
+    free(delta); free(inside); free(S); free(Ss);
+    return rc;
+}
+
 int orc_reconstruct_ext(const orc_grid *g, const orc_camera *cams, int32_t V, int32_t C, double step_vox,
                         double albedo, double background, int32_t s_res, int32_t n_dirs, double s_step,
                         double phase_g, const double *frames, const double *sig, double *em_io, int32_t iters,
                         const orc_recon_params *rp, double *resid_out, int32_t *iters_done)
 {
+    if (rp->subsets > 1)
+        return reconstruct_subsets(g, cams, V, C, step_vox, albedo, background, s_res, n_dirs, s_step, phase_g,
+                                   frames, sig, em_io, iters, rp, iters_done);
     long N = grid_nodes(g);
     long HW = (long)cams[0].width * cams[0].height;
     long NI = (long)V * C * HW;
