@@ -125,7 +125,15 @@ typedef enum {
  *                negative number).
  *  stop_tol      > 0: stop once the image RMS over the adjusted pixels of two
  *                successive iterations differs by less (Sec. 3; the paper
- *                uses 0.01 on its 0-255 scale); iters is then a maximum. */
+ *                uses 0.01 on its 0-255 scale); iters is then a maximum.
+ *  ordered_subsets  0 or 1: every update uses all views at once. n > 1
+ *                (n <= views): ordered subsets, the classic per-view form
+ *                of SART (n = views) and OS-EM: view v belongs to subset
+ *                v mod n, and an iteration makes n updates in subset order,
+ *                each the rule above restricted to the subset's rays (its
+ *                own row and column sums). The in-scatter grid is refreshed
+ *                once per iteration. Not combined with stop_tol or g_sigma
+ *                (RTE_ERR_UNSUPPORTED) nor with jobs. */
 typedef struct {
     int32_t update;
     float lambda;
@@ -138,6 +146,7 @@ typedef struct {
     int32_t use_hull;
     float outside_value;
     float stop_tol;
+    int32_t ordered_subsets;
 } rte_recon_params;
 
 /* Colour-temperature mapping (Eq. 13; Sec. 3.3). The LUT holds, at lut_size

@@ -181,7 +181,9 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     const int C = params->channels;
     const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
     const bool grads = (params->flags & RTE_PLAN_GRADIENTS) != 0;
-    s.part_acc = std::max(grads ? C + 1 : C, 2);
+    // C + 1 accumulators per corner: room for a gather with column sums
+    // (temperature fit, ordered subsets, gradients)
+    s.part_acc = std::max(C + 1, 2);
     s.lut_cap = kMaxLut;
     s.cams = sizeof(rte_camera) * d.V;
     s.proj = sizeof(rte::ViewProj) * d.V;
@@ -725,6 +727,10 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
         return fail(RTE_ERR_INVALID_ARG, "g_sigma must be finite and >= 0");
     if (params->use_hull && plan->V > 64) return fail(RTE_ERR_UNSUPPORTED, "the visual hull supports at most 64 views");
     if (!(params->stop_tol >= 0.0f)) return fail(RTE_ERR_INVALID_ARG, "stop_tol must be >= 0");
+    const int nsub = std::max(1, (int)params->ordered_subsets);
+    if (nsub > plan->V) return fail(RTE_ERR_INVALID_ARG, "ordered_subsets (%d) exceeds the views (%d)", nsub, plan->V);
+    if (nsub > 1 && (params->stop_tol > 0.0f || params->g_sigma != 0.0f))
+        return fail(RTE_ERR_UNSUPPORTED, "ordered subsets are not combined with the stop rule or the gains G(s)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
     plan->last_iters = 0;
@@ -745,15 +751,42 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
     }
     if (upd != RTE_UPDATE_PAPER && iters > 0) {
         // row sums come out of every render; column sums A^T 1 (over the
-        // adjusted rays) once per call
+        // adjusted rays) once per call, or per subset along with each
+        // subset's gather
         RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-        RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
-                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
-        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
-                   rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
+        if (nsub == 1) {
+            RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
+                       rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
+            RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                       rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
+        }
     }
     const int epi = upd == RTE_UPDATE_SART ? rte::kEpiSart : (upd == RTE_UPDATE_MLEM ? rte::kEpiMlem : rte::kEpiPaper);
+    if (nsub > 1) {
+        // ordered subsets: view v in subset v mod nsub; one update per subset
+        const bool paper = upd == RTE_UPDATE_PAPER;
+        const int gmode = paper ? rte::kGatherPaper : rte::kGatherAdjointCols;
+        const int umode = paper ? rte::kUpdPaper : (upd == RTE_UPDATE_SART ? rte::kUpdSartOS : rte::kUpdMlemOS);
+        const int acc = paper ? C : C + 1;
+        for (int it = 0; it < iters; ++it) {
+            if (scat) RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, nullptr, s));
+            for (int sb = 0; sb < nsub; ++sb) {
+                RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
+                           rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s, nullptr,
+                                              mask, nullptr, nsub, sb));
+                RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                           rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau,
+                                              s, paper ? nullptr : mask, 0.f, 0, it, sb, nsub));
+                RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                           rte::launch_update(plan, C, acc, umode, params->lambda, params->clamp_nonneg, nullptr,
+                                              nullptr, 0, 0, s, nullptr, inside));
+            }
+            plan->last_iters = it + 1;
+        }
+        RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_unpack(plan, emission, C, s));
+        return ok();
+    }
     const int gmode = upd == RTE_UPDATE_PAPER ? rte::kGatherPaper : rte::kGatherAdjoint;
     const int umode = upd == RTE_UPDATE_SART ? rte::kUpdSart : (upd == RTE_UPDATE_MLEM ? rte::kUpdMlem : rte::kUpdPaper);
     double prev_err = 0.0;

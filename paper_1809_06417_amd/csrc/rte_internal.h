@@ -43,6 +43,8 @@ enum UpdateMode : int {
     kUpdPaper = 4,   // e += sum
     kUpdTemp = 5,    // EM on the fitted channel, clamp to LUT, invert to T
     kUpdGrad = 6,    // out[c][j] = sum_c, out2[j] = sum_C (emission / extinction gradients)
+    kUpdSartOS = 7,  // SART with the column sums gathered alongside (sum_C): ordered subsets
+    kUpdMlemOS = 8,  // EM likewise
 };
 
 // Per-view projection from voxel coordinates to homogeneous pixel
@@ -146,14 +148,14 @@ hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
                          int frame_channel0, float *out, hipStream_t s, float *exit_T = nullptr,
-                         const float *mask = nullptr, float2 *err = nullptr);
+                         const float *mask = nullptr, float2 *err = nullptr, int sub_n = 1, int sub_s = 0);
 hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
                                 hipStream_t s);
 hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,
                          float alpha_l, float alpha_d, float tau, hipStream_t s,
                          const float *rowmask = nullptr, float g_sigma = 0.f, uint64_t seed = 0,
-                         int iteration = 0);
+                         int iteration = 0, int view0 = 0, int view_step = 1);
 hipError_t launch_flame_mask(const rte_plan *p, const float *frames, int frame_channels, float threshold,
                              float *mask, hipStream_t s);
 hipError_t launch_hull(const rte_plan *p, const float *mask, int32_t *inside, hipStream_t s);

@@ -548,6 +548,7 @@ struct RenderArgs {
     float *exit_T;  // optional [V][H][W] transmittance at the exit (image renders)
     const float *mask;   // optional [V][H][W] ray mask (1 adjust, 0 ignore) for residual epilogues
     float2 *err;         // optional per-slot (sum of squared residuals, count) over masked pixels
+    int sub_n, sub_s;    // only views v with v % sub_n == sub_s (ordered subsets)
     int fC, fc0;  // frames hold fC channels; channel c of the render reads fc0 + c
     int W, H, tiles_x, tiles_per_view, n_tiles, nb8;
     int nx, ny, nz, M;
@@ -572,6 +573,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     // view and the per-view in-scatter grid address) in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(a.tile_order[slot]);
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
+    if (a.sub_n > 1 && v % a.sub_n != a.sub_s) return;  // whole wave: view outside the subset
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
     const bool in_image = px < a.W && py < a.H;
@@ -1111,7 +1113,8 @@ struct GatherArgs {
     float g_sigma;                      // paper mode: spread of the gains G(s)
     uint32_t seed_lo, seed_hi;
     int iteration;
-    const float *rowmask;               // optional [V][H][W]: rays with 0 are skipped (cols, hull)
+    const float *rowmask;               // optional [V][H][W]: rays with 0 are skipped (cols, hull, adjoint+cols)
+    int view0, view_step;               // views view0, view0 + view_step, ... (ordered subsets)
 };
 
 constexpr float kBoxPad = 1e-3f;   // voxels: cell box padding for FP32 sample positions
@@ -1155,7 +1158,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
     const int HW = a.W * a.H;
     uint64_t hull_bits = 0;
 
-    for (int v = 0; v < a.V; ++v) {
+    for (int v = a.view0; v < a.V; v += a.view_step) {
         const float *P = a.proj[v].P;
         bool found = false;  // hull mode: this view already tags the cell
         // project the 8 corners of the padded box
@@ -1188,7 +1191,9 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
             for (int px = u0; px <= u1 && !found; ++px) {
                 const int pix = py * a.W + px;
                 const int r = v * HW + pix;
-                if ((MODE == kGatherCols || MODE == kGatherHull) && a.rowmask && a.rowmask[r] == 0.0f) continue;
+                if ((MODE == kGatherCols || MODE == kGatherHull || MODE == kGatherAdjointCols) && a.rowmask &&
+                    a.rowmask[r] == 0.0f)
+                    continue;
                 const float4 B = a.rayB[r];
                 const float4 A = a.rayA[r];
                 const int K = __float_as_int(B.w);
@@ -1367,7 +1372,8 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
     const int64_t j = (int64_t)blk * kBlock + threadIdx.x;
     if (j >= a.n) return;
     const int jx = (int)(j % a.nx), jy = (int)((j / a.nx) % a.ny), jz = (int)(j / ((int64_t)a.nx * a.ny));
-    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : (MODE == kUpdGrad ? C + 1 : C));
+    constexpr bool kOS = MODE == kUpdSartOS || MODE == kUpdMlemOS;  // column sums in sum[C]
+    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : ((MODE == kUpdGrad || kOS) ? C + 1 : C));
     float sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0f;
@@ -1400,7 +1406,10 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
         a.temperature[j] = lut_invert(row, a.lut_size, e, a.t_min, a.t_max);
     } else {
         if (a.inside && !a.inside[j]) return;
-        const float cs = (MODE == kUpdPaper) ? 1.0f : a.cols[j];
+        float cs;
+        if constexpr (MODE == kUpdPaper) cs = 1.0f;
+        else if constexpr (kOS) cs = sum[C];
+        else cs = a.cols[j];
         if (MODE != kUpdPaper && !(cs > 0.0f)) return;
         float em[C];
         if constexpr (C == 3) {
@@ -1414,8 +1423,8 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             float e = em[q];
-            if constexpr (MODE == kUpdSart) e = fmaf(a.lambda, sum[q] / cs, e);
-            if constexpr (MODE == kUpdMlem) e = e * fmaf(a.lambda, sum[q] / cs - 1.0f, 1.0f);
+            if constexpr (MODE == kUpdSart || MODE == kUpdSartOS) e = fmaf(a.lambda, sum[q] / cs, e);
+            if constexpr (MODE == kUpdMlem || MODE == kUpdMlemOS) e = e * fmaf(a.lambda, sum[q] / cs - 1.0f, 1.0f);
             if constexpr (MODE == kUpdPaper) e = e + sum[q];
             if (a.clamp_nonneg) e = fmaxf(e, 0.0f);
             em[q] = e;
@@ -1704,6 +1713,8 @@ static RenderArgs render_args(const rte_plan *p, int epilogue, const float *fram
                               int frame_channel0, float *out, float *exit_T, const float *mask, float2 *err)
 {
     RenderArgs a{};
+    a.sub_n = 1;
+    a.sub_s = 0;
     a.exit_T = exit_T;
     a.mask = mask;
     a.err = err;
@@ -1745,9 +1756,11 @@ static RenderArgs render_args(const rte_plan *p, int epilogue, const float *fram
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
                          int frame_channel0, float *out, hipStream_t s, float *exit_T, const float *mask,
-                         float2 *err)
+                         float2 *err, int sub_n, int sub_s)
 {
-    const RenderArgs a = render_args(p, epilogue, frames, frame_channels, frame_channel0, out, exit_T, mask, err);
+    RenderArgs a = render_args(p, epilogue, frames, frame_channels, frame_channel0, out, exit_T, mask, err);
+    a.sub_n = sub_n;
+    a.sub_s = sub_s;
     if (channels == 3) return render_dispatch<3>(a, use_emission, use_scatter, write_g, epilogue, s);
     return render_dispatch<1>(a, use_emission, use_scatter, write_g, epilogue, s);
 }
@@ -1863,6 +1876,8 @@ static GatherArgs gather_args(const rte_plan *p, const float *y, float alpha_l, 
                               const float *rowmask, float g_sigma, uint64_t seed, int iteration)
 {
     GatherArgs a{};
+    a.view0 = 0;
+    a.view_step = 1;
     a.rowmask = rowmask;
     a.g_sigma = g_sigma;
     a.seed_lo = (uint32_t)seed;
@@ -1899,9 +1914,17 @@ static GatherArgs gather_args(const rte_plan *p, const float *y, float alpha_l, 
 
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y, float alpha_l,
                          float alpha_d, float tau, hipStream_t s, const float *rowmask, float g_sigma,
-                         uint64_t seed, int iteration)
+                         uint64_t seed, int iteration, int view0, int view_step)
 {
-    const GatherArgs a = gather_args(p, y, alpha_l, alpha_d, tau, rowmask, g_sigma, seed, iteration);
+    if (view_step < 1 || view0 < 0) return hipErrorInvalidValue;
+    // accumulators per corner this mode writes must fit the partial buffer
+    const int need = mode == kGatherCols ? 1
+                     : mode == kGatherHull ? 2
+                     : ((mode == kGatherAdjointCols || mode == kGatherGrad) ? channels + 1 : channels);
+    if (need > p->part_acc) return hipErrorInvalidValue;
+    GatherArgs a = gather_args(p, y, alpha_l, alpha_d, tau, rowmask, g_sigma, seed, iteration);
+    a.view0 = view0;
+    a.view_step = view_step;
     if (channels == 3) {
         switch (mode) {
         case kGatherAdjoint: gather_launch<3, kGatherAdjoint>(a, s); break;
@@ -1980,6 +2003,8 @@ hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, flo
         RTE_UPD(kUpdMlem)
         RTE_UPD(kUpdPaper)
         RTE_UPD(kUpdGrad)
+        RTE_UPD(kUpdSartOS)
+        RTE_UPD(kUpdMlemOS)
     case kUpdTemp: update_launch<1, kUpdTemp>(a, s); break;
     default: return hipErrorInvalidValue;
     }

@@ -57,7 +57,7 @@ class ReconParams(ct.Structure):
                 ("alpha_l", ct.c_float), ("alpha_d", ct.c_float), ("tau", ct.c_float),
                 ("g_sigma", ct.c_float), ("seed", ct.c_uint64), ("use_mask", ct.c_int32),
                 ("flame_threshold", ct.c_float), ("use_hull", ct.c_int32),
-                ("outside_value", ct.c_float), ("stop_tol", ct.c_float)]
+                ("outside_value", ct.c_float), ("stop_tol", ct.c_float), ("ordered_subsets", ct.c_int32)]
 
 
 class _TempParams(ct.Structure):
@@ -309,16 +309,18 @@ class Plan:
 
     def reconstruct(self, frames, extinction, emission, iters, update="sart", lam=1.0,
                     clamp_nonneg=True, alpha_l=1e-3, alpha_d=1.0, tau=0.05, g_sigma=0.0, seed=0,
-                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0):
+                    flame_threshold=None, hull=False, outside_value=0.0, stop_tol=0.0, subsets=1):
         """In place on `emission` (warm start); returns it. flame_threshold
         (not None) restricts the adjustment to flame rays, hull=True to the
-        visual hull; stop_tol > 0 turns on the stop rule (see stats())."""
+        visual hull; stop_tol > 0 turns on the stop rule (see stats());
+        subsets > 1 makes ordered-subset updates (views v mod subsets)."""
         C = self.channels
         rp = ReconParams(update=UPDATES[update], lam=lam, clamp_nonneg=1 if clamp_nonneg else 0,
                          alpha_l=alpha_l, alpha_d=alpha_d, tau=tau, g_sigma=g_sigma, seed=int(seed),
                          use_mask=0 if flame_threshold is None else 1,
                          flame_threshold=0.0 if flame_threshold is None else flame_threshold,
-                         use_hull=1 if hull else 0, outside_value=outside_value, stop_tol=stop_tol)
+                         use_hull=1 if hull else 0, outside_value=outside_value, stop_tol=stop_tol,
+                         ordered_subsets=int(subsets))
         _check(lib().rte_reconstruct(self._h, _ptr(frames, self.img_shape(), "frames"),
                                      _ptr(extinction, self.vol_shape, "extinction"),
                                      _ptr(emission, (C,) + self.vol_shape, "emission"), int(iters),
