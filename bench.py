@@ -94,6 +94,28 @@ def inscatter_samples(n: int, M: int, ndirs: int, s_step: float = 0.5) -> int:
     return total
 
 
+def copy_bandwidth(gib: float = 2.0, reps: int = 5) -> float:
+    """Achievable HBM bandwidth (GB/s, read + write) of a plain device copy of
+    `gib` GiB, median of `reps` timed copies."""
+    import torch
+    n = int(gib * 2**30) // 4
+    src = torch.empty(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    times.sort()
+    return 2 * n * 4 / times[len(times) // 2] / 1e9
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for f in ("rte_kernels.hip",):
@@ -137,9 +159,40 @@ def cpu_baseline(g, rig, em, sig, frames, wl, views):
     y = np.where(R[:, None] > 0, (F - I) / np.where(R[:, None] > 0, R[:, None], 1.0), 0.0)
     oracle.backproject_adjoint(g, sub, sig64, y)
     dt = time.perf_counter() - t0
-    return dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"one FP64 iteration (in-scatter grid, render, back-projection) on "
-                       f"{views} of {rig.n_views} views: {samples} samples in {dt:.1f} s")
+    out = dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
+               sample=f"one FP64 iteration (in-scatter grid, render, back-projection) on "
+                      f"{views} of {rig.n_views} views: {samples} samples in {dt:.1f} s",
+               cpu=cpu_model())
+    # the same on one thread, over one view (the in-scatter grid is computed in full)
+    threads = oracle.num_threads()
+    one = rig.subset([0])
+    _, _, K1 = oracle.ray_table(g, one, 0.5)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        S1 = None
+        if wl["albedo"] > 0:
+            S1 = oracle.inscatter(g, em64, sig64, s_res=wl["M"], n_dirs=wl["dirs"], phase_g=wl.get("phase_g", 0.0),
+                                  rig=one)
+        I1, R1 = oracle.render(g, one, em64, sig64, albedo=wl["albedo"], inscatter=S1, rowsum=True)
+        y1 = np.where(R1[:, None] > 0, (F[:1] - I1) / np.where(R1[:, None] > 0, R1[:, None], 1.0), 0.0)
+        oracle.backproject_adjoint(g, one, sig64, y1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["single_thread"] = dict(value=int(K1.sum()) / dt1, unit="samples/s",
+                                sample=f"one view: {int(K1.sum())} samples in {dt1:.1f} s (in-scatter grid included)")
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs visible)"
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -276,10 +329,11 @@ def main():
     achieved = cands[dom] / dom_avg_s / 1e9
     traffic = load_traffic(dom, args.workload)
     n_units = scat_samples if dom == "inscatter" else samples
+    achievable = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "bytes_per_sample": cands[dom] // n_units, "samples_per_launch": n_units,
-                "avg_ms": round(dom_avg_s * 1e3, 4),
+                "avg_ms": round(dom_avg_s * 1e3, 4), "achievable_copy_GBs": round(achievable, 1),
                 "all": {k: {"avg_ms": round(ktimes[k][0] / max(ktimes[k][1], 1), 4),
                             "achieved_GBs": round(v / (ktimes[k][0] / max(ktimes[k][1], 1) / 1e3) / 1e9, 1)}
                         for k, v in cands.items() if ktimes[k][1]}}

@@ -15,7 +15,7 @@ __all__ = [
     "lib", "ray_table", "render", "inscatter", "backproject_adjoint", "backproject_paper",
     "reconstruct", "planck", "band_radiance", "TempParams", "temp_lut", "temp_map",
     "temp_invert", "temperature_fit", "num_threads", "render_grad", "philox4x32_10",
-    "sample_gain", "flame_mask", "visual_hull", "reconstruct_ext", "suggest_grid",
+    "sample_gain", "flame_mask", "visual_hull", "reconstruct_ext", "suggest_grid", "set_num_threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,12 +90,18 @@ def lib():
         _lib.orc_temperature_fit.argtypes = [P(_Grid), P(_Camera), i32, d, P(_TempParams), dp, dp,
                                              dp, i32, d, dp]
         _lib.orc_num_threads.restype = ct.c_int
+        _lib.orc_set_num_threads.argtypes = [i32]
+        _lib.orc_set_num_threads.restype = None
         _lib.orc_suggest_grid.argtypes = [P(_Camera), i32, dp, dp, d, P(ct.c_int32), dp]
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def suggest_grid(rig, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), alpha=1.5):

@@ -1466,3 +1466,14 @@ int orc_suggest_grid(const orc_camera *cams, int32_t V, const double lo[3], cons
 }
 
 int orc_num_threads(void) { return n_threads(); }
+
+/* Threads the parallel loops use from now on (1 .. 32); results depend on
+ * the count only through the fixed-order reduction of private sums. */
+void orc_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n < 1 ? 1 : (n > ORC_MAX_THREADS ? ORC_MAX_THREADS : n));
+#else
+    (void)n;
+#endif
+}
