@@ -57,6 +57,9 @@ WORKLOADS = {
     # degree elevations; grid from the volume-dimension rule (alpha = 1.5);
     # reconstruct from 9 views, measure the held-out one
     "lovo": dict(n=0, views=10, W=640, H=480, C=3, albedo=0.3, M=32, dirs=32, iters=20),
+    # camera-count sweep of the temperature reconstruction (Sec. 5.2): rings of
+    # 4, 16 and 28 cameras, 30 iterations each
+    "sweep": dict(n=128, views=0, W=256, H=256, C=1, albedo=0.0, M=0, dirs=32, iters=30, counts=(4, 16, 28)),
     "serve": dict(n=0, views=0, W=0, H=0, C=3, albedo=0.0, M=0, dirs=32, iters=10,
                   videos=6, rate=40.0),
 }
@@ -237,6 +240,8 @@ def main():
         return run_serve(args, wl)
     if args.workload == "lovo":
         return run_lovo(args, wl)
+    if args.workload == "sweep":
+        return run_sweep(args, wl)
     print(f"[bench] workload {args.workload}: building inputs", file=sys.stderr, flush=True)
     if args.workload in ("colour", "colour_hg", "diff"):
         g, em, sig = synth.colour_volume(args.seed, n=wl["n"])
@@ -417,6 +422,38 @@ def run_lovo(args, wl):
                      "bytes_per_sample": b_render, "samples_per_launch": samples},
         "cpu_baseline": None,
         "kernels": {k: {"avg_ms": ms_ / n_, "launches": n_} for k, (ms_, n_) in r["kernels"].items() if n_},
+    }
+    print(json.dumps(out))
+
+
+def run_sweep(args, wl):
+    """Camera-count sweep of the temperature fit; a step is one fit iteration,
+    summed over the rigs."""
+    import torch
+
+    import synth
+    from paper_1809_06417_amd import evaluate
+
+    g, T = synth.temperature_volume(args.seed, n=wl["n"])
+    Td = torch.tensor(T.astype("float32"), device="cuda")
+    rigs = [synth.ring_rig(n, wl["W"], wl["H"], elevation_jitter_deg=10.0, seed=args.seed) for n in wl["counts"]]
+    evaluate.camera_sweep(g, Td, rigs[:1], 2)  # warm-up
+    res = evaluate.camera_sweep(g, Td, rigs, wl["iters"])
+    samples = sum(r["samples_per_iter"] for r in res)
+    secs = sum(r["reconstruct_s"] for r in res)
+    value = samples * wl["iters"] / secs
+    out = {
+        "metric": "ray samples/s per render+backproject iteration", "value": value, "unit": "samples/s",
+        "n_gpus": 1, "steps": wl["iters"] * len(rigs), "warmup": 2,
+        "ms_per_step": secs / (wl["iters"] * len(rigs)) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sweep: temperature fit on the {wl['n']}^3 plume field with rings of "
+                               f"{', '.join(str(n) for n in wl['counts'])} cameras at {wl['W']}x{wl['H']}, "
+                               f"{wl['iters']} iterations from 800 K each"},
+        "evaluation": [{"cameras": r["cameras"], "pixel_rmse_rgb": [round(float(v), 3) for v in r["image"]],
+                        "temperature_rmse_K": round(r["temperature_K"], 2), "hull_voxels": r["voxels"],
+                        "seconds": round(r["reconstruct_s"], 4)} for r in res],
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))
 

@@ -135,11 +135,12 @@ def camera_sweep(grid, temperature, rigs, iters, *, temp=None, flame_frac=0.01, 
             I = torch.stack([p.render(e3[c:c + 1].contiguous(), s3)[:, 0] for c in range(3)], dim=1)
             thr = flame_frac * float(F.max())
             inside = p.visual_hull(p.flame_mask(F[:, 1:2].contiguous(), thr))
+            samples = p.samples
             Fh, Ih = _host(F), _host(I)
             Th, Tg, inside_h, eg = _host(T), _host(temperature), _host(inside), _host(em3[1])
         err = image_rmse(Ih, Fh, flame_boxes(Fh, thr), 255.0 / max(float(Fh.max()), 1e-30))
         mask = inside_h.astype(bool) & (eg >= observable * eg.max())
         t_rmse = float(np.sqrt(((Th - Tg)[mask] ** 2).mean())) if mask.any() else 0.0
         out.append({"cameras": n, "image": err.mean(axis=0), "temperature_K": t_rmse,
-                    "voxels": int(mask.sum()), "reconstruct_s": seconds})
+                    "voxels": int(mask.sum()), "reconstruct_s": seconds, "samples_per_iter": samples})
     return out
