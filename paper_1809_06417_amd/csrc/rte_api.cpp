@@ -863,6 +863,7 @@ int rte_job_begin(rte_plan *plan, const float *frames, const float *extinction, 
     if (upd == RTE_UPDATE_PAPER && !(params->tau >= 0.0f && params->tau < 1.0f))
         return fail(RTE_ERR_INVALID_ARG, "tau must be in [0, 1)");
     if (params->stop_tol != 0.0f) return fail(RTE_ERR_UNSUPPORTED, "jobs run a fixed number of steps (stop_tol = 0)");
+    if (params->ordered_subsets > 1) return fail(RTE_ERR_UNSUPPORTED, "jobs update with all views at once (ordered_subsets <= 1)");
     if (params->use_hull && plan->V > 64) return fail(RTE_ERR_UNSUPPORTED, "the visual hull supports at most 64 views");
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;

@@ -338,14 +338,14 @@ class Plan:
         return temperature
 
     def job_begin(self, frames, extinction, emission=None, update="sart", lam=1.0,
-                  clamp_nonneg=True, flame_threshold=None, hull=False, outside_value=0.0):
+                  clamp_nonneg=True, flame_threshold=None, hull=False, outside_value=0.0, subsets=1):
         """Open a job; emission None keeps the volume resident in the plan."""
         C = self.channels
         rp = ReconParams(update=UPDATES[update], lam=lam, clamp_nonneg=1 if clamp_nonneg else 0,
                          alpha_l=1e-3, alpha_d=1.0, tau=0.05,
                          use_mask=0 if flame_threshold is None else 1,
                          flame_threshold=0.0 if flame_threshold is None else flame_threshold,
-                         use_hull=1 if hull else 0, outside_value=outside_value)
+                         use_hull=1 if hull else 0, outside_value=outside_value, ordered_subsets=int(subsets))
         self._job_frames = frames  # keep the caller's frames alive while the job is open
         _check(lib().rte_job_begin(self._h, _ptr(frames, self.img_shape(), "frames"),
                                    _ptr(extinction, self.vol_shape, "extinction"),

@@ -143,6 +143,8 @@ def test_job_api_rejects_bad_batches():
         F, sig = frame_inputs(SMALL[0], 0)
         with pytest.raises(rte().RteError):
             rte().job_step([a])                       # no open job
+        with pytest.raises(rte().RteError):
+            a.job_begin(dev(F), dev(sig), None, subsets=2)  # ordered subsets: not in jobs
         Fd = dev(F)
         a.job_begin(Fd, dev(sig), torch.zeros((3,) + a.vol_shape, device="cuda"))
         with pytest.raises(rte().RteError):
