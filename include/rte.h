@@ -296,7 +296,8 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
  * previous job (warm start) -- and the frame's extinction, and prepares the
  * flame mask, visual hull and column sums as rte_reconstruct does. frames
  * [V][C][H][W] stays owned by the caller and must stay valid until
- * rte_job_end. params->stop_tol must be 0.
+ * rte_job_end. params->stop_tol must be 0 and params->ordered_subsets <= 1
+ * (RTE_ERR_UNSUPPORTED otherwise).
  * rte_job_step advances every listed plan (1..64 distinct plans with open
  * jobs, one channel count, update rule and scattering setting) by one
  * iteration with one launch per phase covering all of them; each plan's
