@@ -3,7 +3,9 @@ shape (including fewer than 8 key points per axis), boxes off the unit cube,
 1-3 cameras anywhere outside or inside the box with random orientation and
 field of view, ragged images of 1-23 pixels per side, one or three channels.
 Render and adjoint back-projection through the C ABI against the FP64
-oracle at every generated case."""
+oracle at every generated case; three iterations of reconstruction (SART, EM
+or the paper's update; ordered subsets; in-scattering with or without the
+phase function; flame mask and visual hull) likewise."""
 import numpy as np
 import pytest
 
@@ -79,3 +81,58 @@ def test_random_render_and_backprojection_match_oracle(case):
         assert rel_max(d, bref) <= BACKPROJ_REL
     else:
         assert np.abs(d).max() == 0.0
+
+
+def random_case(rng, min_views=1):
+    """A case of the same family as `cases`, drawn from a numpy generator."""
+    nx, ny, nz = (int(n) for n in rng.integers(2, 15, 3))
+    lo, ext = rng.uniform(-1.0, 1.0, 3), rng.uniform(0.3, 2.0, 3)
+    V = int(rng.integers(min_views, 4))
+    W, H = (int(n) for n in rng.integers(1, 24, 2))
+    C = int(rng.choice([1, 3]))
+    return nx, ny, nz, lo, ext, V, W, H, C, int(rng.integers(0, 2**31 - 1)), bool(rng.integers(0, 2))
+
+
+# every combination of update rule, ordered subsets, in-scattering and
+# restriction, each on its own random geometry
+RECON_COMBOS = [(u, n, s, r) for u in ("sart", "mlem", "paper") for n in (1, 2)
+                for s in ("none", "iso", "hg") for r in ("none", "mask", "hull")]
+
+
+@pytest.mark.parametrize("combo", range(len(RECON_COMBOS)))
+def test_random_reconstruction_matches_oracle(combo):
+    update, subsets, scat, restrict = RECON_COMBOS[combo]
+    rng = np.random.default_rng(1000 + combo)
+    base = list(random_case(rng, min_views=subsets))
+    if scat != "none":
+        base[8] = 3
+    g, rig, em, sig = build(*base)
+    C = em.shape[0]
+    scatter, phase_g = scat != "none", (0.6 if combo % 2 else -0.4) if scat == "hg" else 0.0
+    masked, hull = restrict != "none", restrict == "hull"
+    M = 4 if scatter else 0
+    kw = dict(step_vox=0.5, albedo=0.3 if scatter else 0.0, background=0.0)
+    S = oracle.inscatter(g, as64(em), as64(sig), s_res=4, n_dirs=8, phase_g=phase_g, rig=rig) if scatter else None
+    F = f32(oracle.render(g, rig, as64(em), as64(sig), inscatter=S, **kw))
+    thr = float(np.float32(0.05 * F.max())) if masked else None
+    x0 = np.full(em.shape, 0.1)
+    ref, _, _ = oracle.reconstruct_ext(g, rig, as64(F), as64(sig), x0, 3, s_res=4, n_dirs=8, phase_g=phase_g,
+                                       mode=update, subsets=subsets, flame_threshold=thr, hull=hull,
+                                       outside_value=0.0, **kw)
+    say("random reconstruction", base[:3], "views", base[5], "image", base[6:8], "C", C, update, "subsets", subsets,
+        "scatter", scat, phase_g, restrict, "seed", base[9])
+    with rte().Plan(g, rig, channels=C, scatter_res=M, scatter_dirs=8, phase_g=phase_g, **kw) as p:
+        x = host(p.reconstruct(dev(F), dev(sig), dev(x0), 3, update=update, subsets=subsets,
+                               flame_threshold=thr, hull=hull))
+    scale = np.abs(ref).max()
+    if scale == 0:
+        assert np.abs(x).max() == 0.0
+        return
+    same = np.ones(x.shape, dtype=bool)
+    if hull:
+        # key points on the hull boundary may be decided differently in FP32 and FP64
+        inside_o = oracle.visual_hull(g, rig, oracle.flame_mask(as64(F), thr), step_vox=0.5)
+        same = np.broadcast_to(inside_o, x.shape)
+        if not same.any():
+            return
+    assert np.sqrt(np.mean((x - ref)[same] ** 2)) / scale <= 1e-3
