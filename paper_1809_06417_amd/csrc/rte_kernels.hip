@@ -417,7 +417,17 @@ __device__ __forceinline__ void scat_sample(const __amdgpu_buffer_rsrc_t &sr, co
 // from memory. The corner values are the same either way.
 constexpr int kWin = 8;
 
-__device__ __forceinline__ int win_slot(int x, int y, int z) { return (x & 7) | ((y & 7) << 3) | ((z & 7) << 6); }
+// Slot of node (x, y, z) (coordinates mod 8). The LDS banks serve a 16-byte
+// node per 4 banks, so the low bits of the slot pick the bank group; in the
+// plain (x, y, z) order those bits are x and the low bit of y, and the rays of
+// a pixel row, which sit side by side across the march direction, hit the same
+// group 3-4 at a time. XOR-ing all three coordinates into the low bits spreads
+// any row across the groups; the map stays a bijection of the 512 slots
+// (z from the top bits, then y, then x).
+__device__ __forceinline__ int win_slot(int x, int y, int z)
+{
+    return ((x ^ y ^ (z << 1)) & 7) | (((y ^ z) & 7) << 3) | ((z & 7) << 6);
+}
 
 template <int C>
 __device__ __forceinline__ typename Packed<C>::T vload(__amdgpu_buffer_rsrc_t r, int off)
