@@ -136,6 +136,29 @@ struct VolCorners {
     T v[8];
 };
 
+// Trilinear interpolation of the 8 corner values, corners in index order
+// (every sampler of the packed volume uses these products in this order).
+template <int C>
+__device__ __forceinline__ void interp_corners(const typename Packed<C>::T v[8], const float w[8], float em[C],
+                                               float &sig)
+{
+    sig = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) em[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if constexpr (C == 3) {
+            em[0] = fmaf(w[c], v[c].x, em[0]);
+            em[1] = fmaf(w[c], v[c].y, em[1]);
+            em[2] = fmaf(w[c], v[c].z, em[2]);
+            sig = fmaf(w[c], v[c].w, sig);
+        } else {
+            em[0] = fmaf(w[c], v[c].x, em[0]);
+            sig = fmaf(w[c], v[c].y, sig);
+        }
+    }
+}
+
 template <int C>
 __device__ __forceinline__ void sample_volume_rsrc(__amdgpu_buffer_rsrc_t r, const int coff[8], int base_bytes,
                                                    const float w[8], VolCorners<C> &vc, float em[C], float &sig)
@@ -148,21 +171,7 @@ __device__ __forceinline__ void sample_volume_rsrc(__amdgpu_buffer_rsrc_t r, con
             else vc.v[c] = bload2(r, base_bytes, coff[c]);
         }
     }
-    sig = 0.0f;
-#pragma unroll
-    for (int c = 0; c < C; ++c) em[c] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if constexpr (C == 3) {
-            em[0] = fmaf(w[c], vc.v[c].x, em[0]);
-            em[1] = fmaf(w[c], vc.v[c].y, em[1]);
-            em[2] = fmaf(w[c], vc.v[c].z, em[2]);
-            sig = fmaf(w[c], vc.v[c].w, sig);
-        } else {
-            em[0] = fmaf(w[c], vc.v[c].x, em[0]);
-            sig = fmaf(w[c], vc.v[c].y, sig);
-        }
-    }
+    interp_corners<C>(vc.v, w, em, sig);
 }
 
 __device__ __forceinline__ void corner_offsets(int nx, int nxy, int elem, int coff[8])
@@ -934,8 +943,10 @@ struct ScatArgs {
 // the partial sums for the next pass. Every sample is taken exactly once, in
 // the same order and arithmetic as a single march, so the sums are those of
 // one march; the working set of a pass is one slab instead of the volume.
-// Each (direction, node) sum is stored; the directions are added in order by
-// inscatter_reduce_kernel.
+// The march is software-pipelined: the corner loads of the next sample are
+// issued before the current sample is accumulated (the loads wait on memory,
+// the sums on nothing but the loads). Each (direction, node) sum is stored;
+// the directions are added in order by inscatter_reduce_kernel.
 template <int C>
 __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
 {
@@ -986,29 +997,60 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
     const bool up = u.z >= 0.0f, last = a.pass == a.npass - 1;
     const int slab = up ? a.pass : a.npass - 1 - a.pass;
     const float zlo = (float)slab * a.slab_h, zhi = (float)(slab + 1) * a.slab_h;
-    int k = k0;
-    for (; k < K; ++k) {
-        float s, len;
-        segment_of(k, K, ell, a.ds, s, len);
-        const float zs = fmaf(s, u.z, pz);
-        if (!last && (up ? zs >= zhi : zs < zlo)) break;
+    // software pipeline: the corner loads of sample k + 1 are in flight
+    // while sample k is accumulated (the positions do not depend on the sums)
+    using PT = typename Packed<C>::T;
+    auto locate = [&](int kk, float &len, float &zs, int &base, float &fx, float &fy, float &fz) {
+        float s;
+        segment_of(kk, K, ell, a.ds, s, len);
+        zs = fmaf(s, u.z, pz);
         int ix, iy, iz;
-        float fx, fy, fz;
         cell_of(fmaf(s, u.x, px), a.nx, ix, fx);
         cell_of(fmaf(s, u.y, py), a.ny, iy, fy);
         cell_of(zs, a.nz, iz, fz);
+        base = ((int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix) * elem;
+    };
+    auto fetch = [&](int base, PT v[8]) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if constexpr (C == 3) v[c] = bload4(vr, base, coff[c]);
+            else v[c] = bload2(vr, base, coff[c]);
+        }
+    };
+    int k = k0;
+    PT cur[8];
+    float len = 0.f, zs = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    if (k < K) {
+        int base;
+        locate(k, len, zs, base, fx, fy, fz);
+        fetch(base, cur);
+    }
+    for (; k < K; ++k) {
+        if (!last && (up ? zs >= zhi : zs < zlo)) break;
+        PT nxt[8];
+        float len2 = 0.f, zs2 = 0.f, fx2 = 0.f, fy2 = 0.f, fz2 = 0.f;
+        int base2 = 0;
+        if (k + 1 < K) {
+            locate(k + 1, len2, zs2, base2, fx2, fy2, fz2);
+            fetch(base2, nxt);
+        }
         float wt[8];
         tri_weights(fx, fy, fz, wt);
         float em[C], sig;
-        const int base = (int)(__umul24(iz, nxy) + __umul24(iy, nx)) + ix;
-        VolCorners<C> vcc;  // samples here are two fine cells apart: no reuse to keep
-        sample_volume_rsrc<C>(vr, coff, base * elem, wt, vcc, em, sig);
+        interp_corners<C>(cur, wt, em, sig);
         sig = fmaxf(sig, 0.0f);
         float e;
         const float wg = T * len * phi_exp(sig * len, e);
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = fmaf(wg, em[c], acc[c]);
         T *= e;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
+        len = len2;
+        zs = zs2;
+        fx = fx2;
+        fy = fy2;
+        fz = fz2;
     }
     if (k == k0 && a.pass > 0) return;  // nothing in this slab: the state stands
     if (!last) {
