@@ -85,7 +85,7 @@ struct rte_plan {
     int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
     int n_active_tiles = 0;
     float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]
-    float *d_q = nullptr;           // gradient plans: per-sample (g_k, q_k) float2 pairs, same layout as d_g
+    float *d_q = nullptr;           // gradient plans: per-sample (g_k, q_k) float2 pairs, tile rows as d_g, sample k of a ray in row K - 1 - k
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)
     float4 *d_scat = nullptr;       // packed in-scatter grid (rgb, 0)
     float4 *d_dirs = nullptr;       // in-scatter directions, voxel units per world unit

@@ -774,7 +774,7 @@ struct GradArgs {
     int scat_vstride;     // as in RenderArgs
     const float *exit_T;  // [V][H][W]
     const float *dI;      // dL/dI [V][C][H][W]
-    float2 *gq;           // per-sample outputs (g_k, q_k), [tile][k][lane]
+    float2 *gq;           // per-sample outputs (g_k, q_k), [tile][K - 1 - k][lane]: row j = step j
     int W, H, tiles_x, tiles_per_view;
     int nx, ny, nz, M;
     float ds, albedo, background;
@@ -789,7 +789,9 @@ struct GradArgs {
 //                        - Delta_k R_c]                      (dL/d sigma_k)
 // with R_c the radiance of everything behind sample k; nothing per sample is
 // kept from the forward pass. sigma_k = max(0, trilinear) passes the
-// derivative where the trilinear value is >= 0.
+// derivative where the trilinear value is >= 0. Step j stores every ray's
+// sample in row j of the tile (sample K - 1 - j of a ray with K samples), so
+// the wave writes one contiguous row per step.
 template <int C, bool SCAT>
 __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
 {
@@ -898,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
             qk = fmaf(y[c], fmaf(-len, R[c], dc), qk);
             R[c] = fmaf(gk, em[c], R[c]);
         }
-        gqp[k * kTileRays] = make_float2(gk, sraw >= 0.0f ? qk : 0.0f);
+        gqp[j * kTileRays] = make_float2(gk, sraw >= 0.0f ? qk : 0.0f);
     }
 }
 
@@ -1155,7 +1157,7 @@ struct GatherArgs {
     const float4 *rayA, *rayB;
     const uint32_t *tile_off;  // first slot of each tile in the per-sample buffers
     const float *g;
-    const float *q;        // gradient mode: per-sample (g_k, q_k) pairs, float2 [tile][k][lane]
+    const float *q;        // gradient mode: per-sample (g_k, q_k) pairs, float2 [tile][K - 1 - k][lane]
     const float *y;        // residual per ray [V][H][W]: float4 (RGB, pad) for 3 channels, float for 1
     const ViewProj *proj;
     float *part;           // [8][acc][cells]
@@ -1314,7 +1316,8 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                 } else {
                     float gk, qk = 0.0f;
                     if constexpr (MODE == kGatherGrad) {
-                        const float2 gq = reinterpret_cast<const float2 *>(a.q)[(gp - a.g) + k * kTileRays];
+                        // the adjoint march stores sample k in row K - 1 - k
+                        const float2 gq = reinterpret_cast<const float2 *>(a.q)[(gp - a.g) + (K - 1 - k) * kTileRays];
                         gk = gq.x;
                         qk = gq.y;
                     } else {
