@@ -417,7 +417,7 @@ __device__ __forceinline__ void scat_sample(const __amdgpu_buffer_rsrc_t &sr, co
 // LDS window of the packed volume for the rays of one wave (an 8x8 pixel
 // tile). The tile's rays stay close together, so at each step their samples
 // fall in a few cells: the wave keeps an 8x8x8-node window in LDS, addressed
-// toroidally (node (x, y, z) in slot (x & 7, y & 7, z & 7)), and reads the 8
+// toroidally (node (x, y, z) in the slot of (x & 7, y & 7, z & 7)), and reads the 8
 // corners of every sample from it. When a sample leaves the window, the wave
 // moves the window so that it starts at the rays' trailing cells along the
 // march direction and loads only the node planes that enter it (one
@@ -426,16 +426,19 @@ __device__ __forceinline__ void scat_sample(const __amdgpu_buffer_rsrc_t &sr, co
 // from memory. The corner values are the same either way.
 constexpr int kWin = 8;
 
-// Slot of node (x, y, z) (coordinates mod 8). The LDS banks serve a 16-byte
-// node per 4 banks, so the low bits of the slot pick the bank group; in the
-// plain (x, y, z) order those bits are x and the low bit of y, and the rays of
-// a pixel row, which sit side by side across the march direction, hit the same
-// group 3-4 at a time. XOR-ing all three coordinates into the low bits spreads
-// any row across the groups; the map stays a bijection of the 512 slots
-// (z from the top bits, then y, then x).
+// Slot of node (x, y, z) (coordinates mod 8): x + 9 y + 72 z, rows padded to
+// 9 slots. The LDS banks serve a 16-byte node per 4 banks, so the slot mod 16
+// picks the bank group; with the padding, nodes one apart along x, y or the
+// xy diagonal fall in different groups, and the rays of a pixel row, which
+// sit side by side across the march direction, rarely share a group (in
+// plain 8 x 8 x 8 order they did 3-4 at a time). The corners of a cell are
+// the slot plus fixed steps (+1, +9, +72, or -7, -63, -504 where the
+// coordinate wraps from 7 to 0).
+constexpr int kWinPitchY = 9, kWinPitchZ = 72;
+constexpr int kWinSlots = 576;
 __device__ __forceinline__ int win_slot(int x, int y, int z)
 {
-    return ((x ^ y ^ (z << 1)) & 7) | (((y ^ z) & 7) << 3) | ((z & 7) << 6);
+    return (x & 7) + kWinPitchY * (y & 7) + kWinPitchZ * (z & 7);
 }
 
 template <int C>
@@ -535,9 +538,15 @@ struct VolWindow {
         sig = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) em[c] = 0.0f;
+        const int xm = ix & 7, ym = iy & 7, zm = iz & 7;
+        const int b0 = xm + kWinPitchY * ym + kWinPitchZ * zm;
+        const int ox = xm == 7 ? -7 : 1;
+        const int oy = ym == 7 ? -7 * kWinPitchY : kWinPitchY;
+        const int oz = zm == 7 ? -7 * kWinPitchZ : kWinPitchZ;
+        const int sl[8] = {b0, b0 + ox, b0 + oy, b0 + oy + ox, b0 + oz, b0 + oz + ox, b0 + oz + oy, b0 + oz + oy + ox};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const auto v = lds[win_slot(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1))];
+            const auto v = lds[sl[c]];
             if constexpr (C == 3) {
                 em[0] = fmaf(w[c], v.x, em[0]);
                 em[1] = fmaf(w[c], v.y, em[1]);
@@ -620,7 +629,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     float *gp = nullptr;
     if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
     ScatCorners scc;
-    __shared__ typename Packed<C>::T win_lds[4][kWin * kWin * kWin];
+    __shared__ typename Packed<C>::T win_lds[4][kWinSlots];
     VolWindow<C> win;
     win.lds = win_lds[wave];
     {
@@ -830,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     }
     float2 *gqp = a.gq + a.tile_off[tile] + lane;
     ScatCorners scc;
-    __shared__ typename Packed<C>::T win_lds[4][kWin * kWin * kWin];
+    __shared__ typename Packed<C>::T win_lds[4][kWinSlots];
     VolWindow<C> win;
     win.lds = win_lds[wave];
     {
