@@ -1451,6 +1451,7 @@ struct UpdateArgs {
     float t_min, t_max;
     int nx, ny, nz, ncells, acc;
     int bx, by;  // gather bricks (8 x 8 x 4 cells) along x and y
+    int nbx, nby, nblocks;  // update bricks (8 x 8 x 4 key points) along x and y, and their count
     int64_t n;
     float lambda;
     int clamp_nonneg;
@@ -1476,9 +1477,14 @@ __device__ __forceinline__ float lut_invert(const float *row, int L, float x, fl
 template <int C, int MODE>
 __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
 {
-    const int64_t j = (int64_t)blk * kBlock + threadIdx.x;
-    if (j >= a.n) return;
-    const int jx = (int)(j % a.nx), jy = (int)((j / a.nx) % a.ny), jz = (int)(j / ((int64_t)a.nx * a.ny));
+    // one block per brick of 8 x 8 x 4 key points (the cell bricks of the
+    // gather, so the 8-cell reads of a wave are nearly contiguous)
+    if (blk >= a.nblocks) return;
+    const int jx = (blk % a.nbx) * 8 + (threadIdx.x & 7);
+    const int jy = ((blk / a.nbx) % a.nby) * 8 + ((threadIdx.x >> 3) & 7);
+    const int jz = (blk / (a.nbx * a.nby)) * 4 + (threadIdx.x >> 6);
+    if (jx >= a.nx || jy >= a.ny || jz >= a.nz) return;
+    const int64_t j = ((int64_t)jz * a.ny + jy) * a.nx + jx;
     constexpr bool kOS = MODE == kUpdSartOS || MODE == kUpdMlemOS;  // column sums in sum[C]
     constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : ((MODE == kUpdGrad || kOS) ? C + 1 : C));
     float sum[NQ];
@@ -2059,7 +2065,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
 template <int C, int MODE>
 static void update_launch(const UpdateArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((update_kernel<C, MODE>), dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((update_kernel<C, MODE>), dim3(a.nblocks), dim3(kBlock), 0, s, a);
 }
 
 static UpdateArgs update_args(const rte_plan *p, int acc, float lambda, int clamp_nonneg, float *out,
@@ -2086,6 +2092,9 @@ static UpdateArgs update_args(const rte_plan *p, int acc, float lambda, int clam
     a.bx = (p->grid.nx - 1 + 7) / 8;
     a.by = (p->grid.ny - 1 + 7) / 8;
     a.acc = acc;
+    a.nbx = (p->grid.nx + 7) / 8;
+    a.nby = (p->grid.ny + 7) / 8;
+    a.nblocks = a.nbx * a.nby * ((p->grid.nz + 3) / 4);
     a.n = p->n_nodes;
     a.lambda = lambda;
     a.clamp_nonneg = clamp_nonneg;
@@ -2207,7 +2216,7 @@ static hipError_t step_batch(rte_plan *const *plans, int n, bool scat, hipStream
                             q.use_hull ? p->d_inside : nullptr);
         rp[i + 1] = rp[i] + ra[i].nb8;
         gp[i + 1] = gp[i] + ga[i].bx * ga[i].by * ga[i].bz;
-        up[i + 1] = up[i] + blocks_for(ua[i].n);
+        up[i + 1] = up[i] + ua[i].nblocks;
     }
     // staging layout: [render args][gather args][update args][3 prefix tables]
     char *d = static_cast<char *>(plans[0]->d_batch);
