@@ -660,7 +660,8 @@ int rte_render_backward(rte_plan *plan, const float *emission, const float *exti
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
     if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
     RTE_LAUNCH(plan, RTE_KERNEL_ADJOINT, s, rte::launch_adjoint_march(plan, scat, exit_transmittance, grad_images, s));
-    const float *dI = rte::launch_pack_residual(plan, grad_images, s);
+    const float *dI = nullptr;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_residual(plan, grad_images, &dI, s));
     RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_gather(plan, C, rte::kGatherGrad, dI, 0.f, 0.f, 0.f, s));
     RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                rte::launch_update(plan, C, C + 1, rte::kUpdGrad, 0.f, 0, grad_emission, nullptr, 0, 0, s,
@@ -695,7 +696,8 @@ int rte_backproject(rte_plan *plan, const float *extinction, const float *residu
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
     const int C = plan->params.channels;
-    const float *y = rte::launch_pack_residual(plan, residual, s);
+    const float *y = nullptr;
+    RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_residual(plan, residual, &y, s));
     if (mode == RTE_BP_ADJOINT) {
         RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, nullptr, extinction, C, s));
         RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,

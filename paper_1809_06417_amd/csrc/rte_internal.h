@@ -142,8 +142,8 @@ hipError_t launch_pack(const rte_plan *p, const float *emission, const float *ex
 hipError_t launch_step_batch(rte_plan *const *plans, int n, hipStream_t s, hipEvent_t *marks = nullptr);
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s);
 // Residuals in the gather's per-ray layout: packs planar [V][3][H][W] into
-// the plan's residual buffer and returns it (one channel: returns planar).
-const float *launch_pack_residual(const rte_plan *p, const float *planar, hipStream_t s);
+// the plan's residual buffer and sets *packed to it (one channel: to planar).
+hipError_t launch_pack_residual(const rte_plan *p, const float *planar, const float **packed, hipStream_t s);
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,

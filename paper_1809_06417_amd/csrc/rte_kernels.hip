@@ -1750,13 +1750,17 @@ __global__ __launch_bounds__(kBlock) void pack_residual_kernel(const float *plan
     out[r] = make_float4(p[0], p[HW], p[2 * HW], 0.0f);
 }
 
-const float *launch_pack_residual(const rte_plan *p, const float *planar, hipStream_t s)
+hipError_t launch_pack_residual(const rte_plan *p, const float *planar, const float **packed, hipStream_t s)
 {
-    if (p->params.channels != 3) return planar;  // one channel: the layouts agree
+    if (p->params.channels != 3) {  // one channel: the layouts agree
+        *packed = planar;
+        return hipSuccess;
+    }
     const int64_t n = (int64_t)p->V * p->W * p->H;
     hipLaunchKernelGGL(pack_residual_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, planar,
                        reinterpret_cast<float4 *>(p->d_y), p->V, p->W * p->H);
-    return p->d_y;
+    *packed = p->d_y;
+    return hipGetLastError();
 }
 
 hipError_t launch_unpack(const rte_plan *p, float *emission, int channels, hipStream_t s)

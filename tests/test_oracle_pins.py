@@ -264,7 +264,7 @@ def test_tiny_workload_errors_fall():
 
 # ------------------------------------------------------ P7 in-scatter closed form
 def exit_length(p, u, lo=0.0, hi=1.0):
-    with np.errstate(divide="ignore"):
+    with np.errstate(divide="ignore", invalid="ignore"):
         t = np.where(u > 0, (hi - p) / u, np.where(u < 0, (lo - p) / u, np.inf))
     return t.min()
 
