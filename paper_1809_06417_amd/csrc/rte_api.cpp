@@ -753,16 +753,11 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
     }
     if (upd != RTE_UPDATE_PAPER && iters > 0) {
         // row sums come out of every render; column sums A^T 1 (over the
-        // adjusted rays) once per call, or per subset along with each
-        // subset's gather
+        // adjusted rays) come out of the first iteration's gather (stored
+        // for the later iterations), or per subset along with each subset's
+        // gather
         RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
                    rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-        if (nsub == 1) {
-            RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
-                       rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
-            RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
-                       rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
-        }
     }
     const int epi = upd == RTE_UPDATE_SART ? rte::kEpiSart : (upd == RTE_UPDATE_MLEM ? rte::kEpiMlem : rte::kEpiPaper);
     if (nsub > 1) {
@@ -807,12 +802,24 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
             if (it >= 1 && std::fabs(prev_err - err) < (double)params->stop_tol) break;
             prev_err = err;
         }
-        RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
-                   rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau, s,
-                                      nullptr, params->g_sigma, params->seed, it));
-        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
-                   rte::launch_update(plan, C, C, umode, params->lambda, params->clamp_nonneg, nullptr,
-                                      nullptr, 0, 0, s, nullptr, inside));
+        if (it == 0 && upd != RTE_UPDATE_PAPER) {
+            // the first gather also accumulates the column sums (over the
+            // adjusted rays: masked rays are skipped, their residual is 0);
+            // the update uses them and keeps them for the later iterations
+            RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                       rte::launch_gather(plan, C, rte::kGatherAdjointCols, plan->d_y, 0.f, 0.f, 0.f, s, mask));
+            RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                       rte::launch_update(plan, C, C + 1, upd == RTE_UPDATE_SART ? rte::kUpdSartOS : rte::kUpdMlemOS,
+                                          params->lambda, params->clamp_nonneg, nullptr, nullptr, 0, 0, s, nullptr,
+                                          inside, plan->d_cols));
+        } else {
+            RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
+                       rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau, s,
+                                          nullptr, params->g_sigma, params->seed, it));
+            RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
+                       rte::launch_update(plan, C, C, umode, params->lambda, params->clamp_nonneg, nullptr,
+                                          nullptr, 0, 0, s, nullptr, inside));
+        }
         plan->last_iters = it + 1;
     }
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_unpack(plan, emission, C, s));

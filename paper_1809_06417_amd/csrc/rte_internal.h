@@ -165,7 +165,7 @@ hipError_t launch_err_reduce(const rte_plan *p, double *out, hipStream_t s);
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
                          int fit_channel, hipStream_t s, float *out2 = nullptr,
-                         const int32_t *inside = nullptr);
+                         const int32_t *inside = nullptr, float *cols_out = nullptr);
 hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, float *sig_planar,
                            bool packed, int lut_size, int fit_channel, float sigma_max,
                            float soot_t0, float soot_span, float t_min, float t_max,

@@ -1444,6 +1444,7 @@ struct UpdateArgs {
     float *cols;         // column sums (read, or written in kUpdCols)
     float *out;          // delta [C][N] (kUpdDelta, kUpdGrad)
     float *out2;         // extinction gradient [N] (kUpdGrad)
+    float *cols_out;     // optional (kUpdSartOS, kUpdMlemOS): also store the column sums here
     const int32_t *inside;  // optional: key points outside the visual hull are not updated
     float *temperature;  // kUpdTemp output
     const float *lut;    // [3][lut_cap]
@@ -1518,6 +1519,9 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
         e = fminf(fmaxf(e, row[0]), row[a.lut_size - 1]);
         a.temperature[j] = lut_invert(row, a.lut_size, e, a.t_min, a.t_max);
     } else {
+        if constexpr (kOS) {
+            if (a.cols_out) a.cols_out[j] = sum[C];
+        }
         if (a.inside && !a.inside[j]) return;
         float cs;
         if constexpr (MODE == kUpdPaper) cs = 1.0f;
@@ -2107,10 +2111,11 @@ static UpdateArgs update_args(const rte_plan *p, int acc, float lambda, int clam
 
 hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, float lambda,
                          int clamp_nonneg, float *out, float *temperature, int lut_size,
-                         int fit_channel, hipStream_t s, float *out2, const int32_t *inside)
+                         int fit_channel, hipStream_t s, float *out2, const int32_t *inside, float *cols_out)
 {
-    const UpdateArgs a =
+    UpdateArgs a =
         update_args(p, acc, lambda, clamp_nonneg, out, temperature, lut_size, fit_channel, out2, inside);
+    a.cols_out = cols_out;
 #define RTE_UPD(M)                                            \
     case M:                                                   \
         if (channels == 3) update_launch<3, M>(a, s);         \
