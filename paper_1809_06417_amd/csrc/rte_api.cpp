@@ -751,14 +751,12 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
         RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                    rte::launch_apply_outside(plan, C, plan->d_inside, params->outside_value, s));
     }
-    if (upd != RTE_UPDATE_PAPER && iters > 0) {
-        // row sums come out of every render; column sums A^T 1 (over the
-        // adjusted rays) come out of the first iteration's gather (stored
-        // for the later iterations), or per subset along with each subset's
-        // gather
-        RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
-                   rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-    }
+    // SART and EM: the per-sample weights g depend on the extinction only, so
+    // the first iteration's render stores them for every later gather; row
+    // sums come out of every render; column sums A^T 1 (over the adjusted
+    // rays) come out of the first iteration's gather (stored for the later
+    // iterations), or per subset along with each subset's gather
+    const bool weights = upd != RTE_UPDATE_PAPER;
     const int epi = upd == RTE_UPDATE_SART ? rte::kEpiSart : (upd == RTE_UPDATE_MLEM ? rte::kEpiMlem : rte::kEpiPaper);
     if (nsub > 1) {
         // ordered subsets: view v in subset v mod nsub; one update per subset
@@ -770,8 +768,8 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
             if (scat) RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, nullptr, s));
             for (int sb = 0; sb < nsub; ++sb) {
                 RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
-                           rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s, nullptr,
-                                              mask, nullptr, nsub, sb));
+                           rte::launch_render(plan, C, true, scat, weights && it == 0, epi, frames, C, 0, plan->d_y,
+                                              s, nullptr, mask, nullptr, nsub, sb));
                 RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s,
                            rte::launch_gather(plan, C, gmode, plan->d_y, params->alpha_l, params->alpha_d, params->tau,
                                               s, paper ? nullptr : mask, 0.f, 0, it, sb, nsub));
@@ -790,8 +788,8 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
     for (int it = 0; it < iters; ++it) {
         if (scat) RTE_LAUNCH(plan, RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plan, nullptr, s));
         RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
-                   rte::launch_render(plan, C, true, scat, false, epi, frames, C, 0, plan->d_y, s, nullptr, mask,
-                                      stop ? plan->d_err : nullptr));
+                   rte::launch_render(plan, C, true, scat, weights && it == 0, epi, frames, C, 0, plan->d_y, s,
+                                      nullptr, mask, stop ? plan->d_err : nullptr));
         if (stop) {
             RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s, rte::launch_err_reduce(plan, plan->d_err_sum, s));
             RTE_HIP(hipMemcpyAsync(plan->h_err_sum, plan->d_err_sum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
