@@ -294,17 +294,22 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
  * rte_job_begin opens a job on a plan: uploads the start volume -- or, with
  * emission == NULL, keeps the emission already resident in the plan from its
  * previous job (warm start) -- and the frame's extinction, and prepares the
- * flame mask, visual hull and column sums as rte_reconstruct does. frames
+ * flame mask and visual hull as rte_reconstruct does. frames
  * [V][C][H][W] stays owned by the caller and must stay valid until
  * rte_job_end. params->stop_tol must be 0 and params->ordered_subsets <= 1
  * (RTE_ERR_UNSUPPORTED otherwise).
  * rte_job_step advances every listed plan (1..64 distinct plans with open
  * jobs, one channel count, update rule and scattering setting) by one
- * iteration with one launch per phase covering all of them; each plan's
- * result is bitwise the one it would get alone. The launch arguments go
- * through a staging buffer of the first plan: issue all steps that share a
- * first plan on one stream. With timing on, the three batched launches are
- * charged to the first plan (RTE_KERNEL_RENDER, _GATHER, _UPDATE).
+ * iteration with one launch per phase covering all of them, except that the
+ * first step of a SART or EM job runs on its own (its render also stores the
+ * per-sample weights and its gather the column sums, as the first iteration
+ * of rte_reconstruct does); each plan's result is bitwise the one it would
+ * get alone and the one rte_reconstruct gives. The batched launch arguments
+ * go through a staging buffer of the first batched plan (the first listed
+ * plan past its first step, or any paper-rule plan): issue all steps that
+ * share it on one stream. With timing on, the three batched launches are
+ * charged to that plan (RTE_KERNEL_RENDER, _GATHER, _UPDATE), a first step's
+ * launches to its own plan.
  * Errors: RTE_ERR_INVALID_ARG for a plan without an open job or listed twice,
  * RTE_ERR_UNSUPPORTED for more than 64 plans or mixed settings; no plan is
  * advanced then.

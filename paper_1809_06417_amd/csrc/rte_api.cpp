@@ -886,14 +886,8 @@ int rte_job_begin(rte_plan *plan, const float *frames, const float *extinction, 
         RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
                    rte::launch_apply_outside(plan, C, plan->d_inside, params->outside_value, s));
     }
-    if (upd != RTE_UPDATE_PAPER) {
-        RTE_LAUNCH(plan, RTE_KERNEL_WEIGHTS, s,
-                   rte::launch_render(plan, C, false, false, true, -1, nullptr, C, 0, nullptr, s));
-        RTE_LAUNCH(plan, RTE_KERNEL_COLSUM, s,
-                   rte::launch_gather(plan, C, rte::kGatherCols, nullptr, 0.f, 0.f, 0.f, s, mask));
-        RTE_LAUNCH(plan, RTE_KERNEL_UPDATE, s,
-                   rte::launch_update(plan, C, 1, rte::kUpdCols, 0.f, 0, nullptr, nullptr, 0, 0, s));
-    }
+    // SART and EM: the per-sample weights and the column sums come out of
+    // the job's first step (see rte_job_step)
     plan->job_open = true;
     plan->job_frames = frames;
     plan->job_params = *params;
@@ -919,12 +913,45 @@ int rte_job_step(rte_plan *const *plans, int32_t n, void *stream)
     const bool scat = p0->params.albedo > 0.0f && p0->params.scatter_res >= 2;
     if (scat)
         for (int i = 0; i < n; ++i) RTE_LAUNCH(plans[i], RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plans[i], nullptr, s));
-    // timing of the batched launches is charged to the first plan
-    rte_plan *p0t = plans[0];
+    // the first step of a SART or EM job runs alone, as the first iteration
+    // of rte_reconstruct does: its render also stores the per-sample weights
+    // and its gather also accumulates the column sums that the later steps
+    // read (so every job's steps give bitwise the rte_reconstruct result)
+    rte_plan *rest[kMaxBatch];
+    int nrest = 0;
+    for (int i = 0; i < n; ++i) {
+        rte_plan *p = plans[i];
+        const rte_recon_params &q = p->job_params;
+        if (p->job_iter > 0 || q.update == RTE_UPDATE_PAPER) {
+            rest[nrest++] = p;
+            continue;
+        }
+        const int C = p->params.channels;
+        const float *mask = q.use_mask ? p->d_mask : nullptr;
+        const bool sart = q.update == RTE_UPDATE_SART;
+        RTE_LAUNCH(p, RTE_KERNEL_RENDER, s,
+                   rte::launch_render(p, C, true, scat, true, sart ? rte::kEpiSart : rte::kEpiMlem, p->job_frames, C,
+                                      0, p->d_y, s, nullptr, mask, nullptr));
+        RTE_LAUNCH(p, RTE_KERNEL_GATHER, s,
+                   rte::launch_gather(p, C, rte::kGatherAdjointCols, p->d_y, 0.f, 0.f, 0.f, s, mask));
+        RTE_LAUNCH(p, RTE_KERNEL_UPDATE, s,
+                   rte::launch_update(p, C, C + 1, sart ? rte::kUpdSartOS : rte::kUpdMlemOS, q.lambda, q.clamp_nonneg,
+                                      nullptr, nullptr, 0, 0, s, nullptr, q.use_hull ? p->d_inside : nullptr,
+                                      p->d_cols));
+    }
+    if (nrest == 0) {
+        for (int i = 0; i < n; ++i) {
+            plans[i]->job_iter += 1;
+            plans[i]->last_stream = s;
+        }
+        return ok();
+    }
+    // timing of the batched launches is charged to the first plan of the batch
+    rte_plan *p0t = rest[0];
     hipEvent_t marks[6] = {};
     if (p0t->timing)
         for (auto &m : marks) m = take_event(p0t);
-    hipError_t e = rte::launch_step_batch(plans, n, s, p0t->timing ? marks : nullptr);
+    hipError_t e = rte::launch_step_batch(rest, nrest, s, p0t->timing ? marks : nullptr);
     if (p0t->timing) {
         const int kid[3] = {RTE_KERNEL_RENDER, RTE_KERNEL_GATHER, RTE_KERNEL_UPDATE};
         for (int k = 0; k < 3; ++k) {
