@@ -376,7 +376,7 @@ enum {
     RTE_KERNEL_TEMP_MAP = 5,
     RTE_KERNEL_PACK = 6,
     RTE_KERNEL_WEIGHTS = 7, /* render pass that only produces per-sample weights */
-    RTE_KERNEL_COLSUM = 8,  /* gather pass for the column sums A^T 1 */
+    RTE_KERNEL_COLSUM = 8,  /* reserved: the column sums A^T 1 come out of the first gather */
     RTE_KERNEL_ADJOINT = 9, /* reverse march of rte_render_backward */
     RTE_KERNEL_COUNT = 10
 };

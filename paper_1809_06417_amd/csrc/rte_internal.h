@@ -29,7 +29,6 @@ enum ResidualMode : int {
 enum GatherMode : int {
     kGatherAdjoint = 0,       // acc_c += g * y_c * w
     kGatherAdjointCols = 1,   // acc_c += g * y_c * w ; acc_C += g * w
-    kGatherCols = 2,          // acc_0 += g * w
     kGatherPaper = 3,         // acc_c += alpha_l y_c (1-tau)^k exp(-alpha_d D)
     kGatherGrad = 4,          // acc_c += g * y_c * w ; acc_C += q * w
     kGatherHull = 5,          // bit v set when a flame ray of view v has a sample in the cell
@@ -37,13 +36,13 @@ enum GatherMode : int {
 
 enum UpdateMode : int {
     kUpdDelta = 0,   // out[c][j] = sum
-    kUpdCols = 1,    // cols[j] = sum
     kUpdSart = 2,    // e += lambda sum / cols (cols > 0)
     kUpdMlem = 3,    // e *= 1 + lambda (sum / cols - 1) (cols > 0)
     kUpdPaper = 4,   // e += sum
     kUpdTemp = 5,    // EM on the fitted channel, clamp to LUT, invert to T
     kUpdGrad = 6,    // out[c][j] = sum_c, out2[j] = sum_C (emission / extinction gradients)
-    kUpdSartOS = 7,  // SART with the column sums gathered alongside (sum_C): ordered subsets
+    kUpdSartOS = 7,  // SART with the column sums gathered alongside (sum_C): ordered subsets and
+                     // the first iteration (which also stores them in cols_out)
     kUpdMlemOS = 8,  // EM likewise
 };
 

@@ -1188,8 +1188,7 @@ constexpr float kPixPad = 2e-3f;   // pixels: projection rounding allowance
 
 template <int C, int MODE>
 struct GatherAcc {
-    static constexpr int N = MODE == kGatherCols ? 1
-                             : MODE == kGatherHull ? 2
+    static constexpr int N = MODE == kGatherHull ? 2
                              : ((MODE == kGatherAdjointCols || MODE == kGatherGrad) ? C + 1 : C);
 };
 
@@ -1256,7 +1255,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
         // one candidate pixel ray: slab test against the padded cell, then
         // every sample of the ray that the render placed in this cell
         auto candidate = [&](int px, int py, int r, const float4 &A, const float4 &B) {
-            if ((MODE == kGatherCols || MODE == kGatherHull || MODE == kGatherAdjointCols) && a.rowmask &&
+            if ((MODE == kGatherHull || MODE == kGatherAdjointCols) && a.rowmask &&
                 a.rowmask[r] == 0.0f)
                 return;
             const int K = __float_as_int(B.w);
@@ -1283,7 +1282,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
             if (s_out >= (float)(K - 1) * a.ds) k_hi = K - 1;
             if (k_lo > k_hi) return;
             float yv[C];
-            if constexpr (MODE != kGatherCols && MODE != kGatherHull) {
+            if constexpr (MODE != kGatherHull) {
                 if constexpr (C == 3) {
                     const float4 y4 = reinterpret_cast<const float4 *>(a.y)[r];
                     yv[0] = y4.x;
@@ -1334,11 +1333,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                     }
                     float w[8];
                     tri_weights(fx, fy, fz, w);
-                    if constexpr (MODE == kGatherCols) {
-                        const float gm = a.rowmask ? gk * a.rowmask[r] : gk;
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) acc[c][0] = fmaf(gm, w[c], acc[c][0]);
-                    } else if constexpr (MODE == kGatherGrad) {
+                    if constexpr (MODE == kGatherGrad) {
                         float gy[C];
 #pragma unroll
                         for (int qq = 0; qq < C; ++qq) gy[qq] = gk * yv[qq];
@@ -1441,7 +1436,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GatherOc
 struct UpdateArgs {
     const float *part;
     float *vol;          // packed volume (updates)
-    float *cols;         // column sums (read, or written in kUpdCols)
+    float *cols;         // column sums (read by kUpdSart, kUpdMlem)
     float *out;          // delta [C][N] (kUpdDelta, kUpdGrad)
     float *out2;         // extinction gradient [N] (kUpdGrad)
     float *cols_out;     // optional (kUpdSartOS, kUpdMlemOS): also store the column sums here
@@ -1487,7 +1482,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
     if (jx >= a.nx || jy >= a.ny || jz >= a.nz) return;
     const int64_t j = ((int64_t)jz * a.ny + jy) * a.nx + jx;
     constexpr bool kOS = MODE == kUpdSartOS || MODE == kUpdMlemOS;  // column sums in sum[C]
-    constexpr int NQ = (MODE == kUpdCols) ? 1 : (MODE == kUpdTemp ? 2 : ((MODE == kUpdGrad || kOS) ? C + 1 : C));
+    constexpr int NQ = MODE == kUpdTemp ? 2 : ((MODE == kUpdGrad || kOS) ? C + 1 : C);
     float sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0f;
@@ -1507,8 +1502,6 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
 #pragma unroll
         for (int q = 0; q < C; ++q) a.out[q * a.n + j] = sum[q];
         a.out2[j] = sum[C];
-    } else if constexpr (MODE == kUpdCols) {
-        a.cols[j] = sum[0];
     } else if constexpr (MODE == kUpdTemp) {
         float2 *vol = reinterpret_cast<float2 *>(a.vol);
         float2 p = vol[j];
@@ -2039,8 +2032,7 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
 {
     if (view_step < 1 || view0 < 0) return hipErrorInvalidValue;
     // accumulators per corner this mode writes must fit the partial buffer
-    const int need = mode == kGatherCols ? 1
-                     : mode == kGatherHull ? 2
+    const int need = mode == kGatherHull ? 2
                      : ((mode == kGatherAdjointCols || mode == kGatherGrad) ? channels + 1 : channels);
     if (need > p->part_acc) return hipErrorInvalidValue;
     GatherArgs a = gather_args(p, y, alpha_l, alpha_d, tau, rowmask, g_sigma, seed, iteration);
@@ -2050,7 +2042,6 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         switch (mode) {
         case kGatherAdjoint: gather_launch<3, kGatherAdjoint>(a, s); break;
         case kGatherAdjointCols: gather_launch<3, kGatherAdjointCols>(a, s); break;
-        case kGatherCols: gather_launch<3, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<3, kGatherPaper>(a, s); break;
         case kGatherGrad: gather_launch<3, kGatherGrad>(a, s); break;
         case kGatherHull: gather_launch<3, kGatherHull>(a, s); break;
@@ -2060,7 +2051,6 @@ hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float 
         switch (mode) {
         case kGatherAdjoint: gather_launch<1, kGatherAdjoint>(a, s); break;
         case kGatherAdjointCols: gather_launch<1, kGatherAdjointCols>(a, s); break;
-        case kGatherCols: gather_launch<1, kGatherCols>(a, s); break;
         case kGatherPaper: gather_launch<1, kGatherPaper>(a, s); break;
         case kGatherGrad: gather_launch<1, kGatherGrad>(a, s); break;
         case kGatherHull: gather_launch<1, kGatherHull>(a, s); break;
@@ -2123,7 +2113,6 @@ hipError_t launch_update(const rte_plan *p, int channels, int acc, int mode, flo
         break;
     switch (mode) {
         RTE_UPD(kUpdDelta)
-        RTE_UPD(kUpdCols)
         RTE_UPD(kUpdSart)
         RTE_UPD(kUpdMlem)
         RTE_UPD(kUpdPaper)
