@@ -62,6 +62,34 @@ def test_job_path_equals_reconstruct(update):
         assert p.stats()[0] == 4
 
 
+@pytest.mark.parametrize("update,restrict", [("sart", "mask"), ("mlem", "hull"), ("paper", "hull")])
+def test_job_path_equals_reconstruct_with_restrictions(update, restrict):
+    """Flame mask and visual hull: a job (its first step run alone, the
+    rest batched with a second job) gives bitwise the rte_reconstruct result."""
+    import torch
+    spec, other = SMALL[1], SMALL[0]
+    F, sig = frame_inputs(spec, 1)
+    thr = float(np.float32(0.05 * F.max()))
+    kw = dict(update=update, flame_threshold=thr, hull=restrict == "hull", outside_value=0.0)
+    say("job vs reconstruct with", update, restrict)
+    with new_plan(spec) as p, new_plan(other) as q:
+        start = dev(np.full((3,) + spec.grid.shape_zyx, 0.05))
+        a = start.clone()
+        p.reconstruct(dev(F), dev(sig), a, 4, **kw)
+        Fq, sq = frame_inputs(other, 0)
+        q.job_begin(dev(Fq), dev(sq), torch.zeros((3,) + q.vol_shape, device="cuda"), update=update)
+        rte().job_step([q])
+        p.job_begin(dev(F), dev(sig), start, **kw)
+        for _ in range(4):
+            rte().job_step([q, p])   # p's first step runs alone, the later ones batched with q
+        b = torch.empty_like(start)
+        p.job_end(b)
+        q.job_end(None)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert p.stats()[0] == 4
+
+
 def test_batched_steps_match_each_job_alone():
     """Three plans of different grids, view counts and image sizes advance
     together; each result is bitwise its result alone."""
