@@ -513,6 +513,9 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
             dirs[k] = make_float4((float)(world[3 * k] / d.h[0]), (float)(world[3 * k + 1] / d.h[1]),
                                   (float)(z / d.h[2]), 0.f);
         }
+        // z decreases with k: the upward directions come first
+        p->scat_nup = 0;
+        while (p->scat_nup < nd && dirs[p->scat_nup].z >= 0.0f) ++p->scat_nup;
         if (hipMemcpyAsync(p->d_dirs, dirs.data(), full.dirs, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(p->d_dirs_world, world.data(), full.dirs_world, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemsetAsync(p->d_scat, 0, full.scat, s) != hipSuccess)

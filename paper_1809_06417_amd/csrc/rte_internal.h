@@ -71,6 +71,7 @@ struct rte_plan {
     double h[3] = {0, 0, 0};
     double ds = 0.0;
     uint64_t samples = 0, hit_rays = 0, g_floats = 0;
+    int scat_nup = 0;  // in-scatter directions 0 .. scat_nup-1 point up (z >= 0), the rest down
     hipStream_t last_stream = nullptr;
 
     // device workspaces (all owned by the plan)

@@ -915,11 +915,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
 
 // ----------------------------------------------------------- K2 in-scatter
 
-// In-scatter slab passes: slabs of at least this many bytes of the packed
-// volume, at most kScatMaxPasses passes (each pass costs a launch; measured
-// on the 128^3 colour workload: 4-8 passes of 4-8 MB take 10% less time
-// than one march, 16 or more passes take longer; with the pipelined march,
-// 2, 3, 4 and 8 passes take 1.03, 1.00, 1.01 and 1.07 of the best).
+// In-scatter slab passes. A packed volume of at most kScatSlabBytes is
+// marched in one pass by all XCDs. A larger one is cut into 8 slabs along z
+// and XCD x marches slab x only, so its L2 (4 MB) holds one slab instead of
+// the volume: on the 128^3 colour workload (33 MB) the march takes 0.56 ms
+// instead of 0.82 ms with 4 slabs of 8 MB marched by all XCDs together; with
+// the same sample count, a 64^3 volume (4 MB) takes 0.29 ms in one pass.
+// (kScatMaxPasses bounds the passes of the older all-XCD slab form, which
+// the one-pass case still uses.)
 constexpr int64_t kScatSlabBytes = 8ll << 20;
 constexpr int kScatMaxPasses = 8;
 
@@ -935,6 +938,9 @@ struct ScatArgs {
     float *planar;       // optional [C][M^3]
     int nx, ny, nz, M, ndirs;
     int nbricks, blocks_per_dir, dirs_per_xcd;
+    int xslab;           // 1: XCD x owns slab x (8 slabs); 0: all XCDs march one slab per pass
+    int nup;             // directions 0 .. nup-1 point up (u.z >= 0), the rest down
+    int bz_lo[8], bz_hi[8];  // xslab: node-brick layers that hold the nodes starting in each slab
     float p_scale[3];    // in-scatter node index -> fine grid coords
     float ds;            // world step
     float inv_ndirs;
@@ -946,15 +952,18 @@ struct ScatArgs {
     double lo[3], hs[3];       // world position of in-scatter node m: lo + m * hs
 };
 
-// Direction-major march in slab passes. XCD x (blocks b with b % 8 == x)
-// takes directions x, x + 8, x + 16, ... (a wave = one 4x4x4 brick of nodes,
-// a block = four bricks). The volume is cut into npass slabs along z, sized
-// to sit in one XCD's L2; pass p advances every ray of direction d through
-// slab p (slab npass - 1 - p when d points down), stopping at the first
-// sample beyond it, and keeps the next sample index, the transmittance and
-// the partial sums for the next pass. Every sample is taken exactly once, in
-// the same order and arithmetic as a single march, so the sums are those of
-// one march; the working set of a pass is one slab instead of the volume.
+// March in slab passes (a wave = one 4x4x4 brick of nodes and one
+// direction, a block = four such waves). Every ray stops at the first sample
+// beyond its slab and keeps the next sample index, the transmittance and the
+// partial sums for the next pass; every sample is taken exactly once, in the
+// same order and arithmetic as a single march, so the sums are those of one
+// march. Two schedules:
+//  * xslab: 8 slabs, XCD x (blocks b with b % 8 == x) owns slab x. Rays are
+//    monotone in z and cross one slab per pass, so in pass p XCD x takes the
+//    up-going rays of the nodes that start in slab x - p and the down-going
+//    rays of those starting in slab x + p; each XCD's working set is its slab.
+//  * otherwise: XCD x takes directions x, x + 8, ..., and pass p advances
+//    every ray through slab p (slab npass - 1 - p when it points down).
 // The march is software-pipelined: the corner loads of the next sample are
 // issued before the current sample is accumulated (the loads wait on memory,
 // the sums on nothing but the loads). Each (direction, node) sum is stored;
@@ -964,15 +973,48 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
 {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int d = x + 8 * (j / a.blocks_per_dir);
-    const int brick = (j % a.blocks_per_dir) * 4 + w;
-    if (d >= a.ndirs || brick >= a.nbricks) return;
     const int M = a.M, bm = (M + 3) >> 2;
-    const int bx = brick % bm, by = (brick / bm) % bm, bz = brick / (bm * bm);
+    int d, bx, by, bz, start = 0;
+    if (a.xslab) {
+        // XCD x marches slab x: in pass p, the up-going rays of the nodes that
+        // start in slab x - p and the down-going rays of those starting in
+        // slab x + p (a ray crosses one slab per pass)
+        const int s_up = x - a.pass, s_dn = x + a.pass;
+        const int bxy = bm * bm;
+        const int nl_up = s_up >= 0 ? max(a.bz_hi[s_up] - a.bz_lo[s_up] + 1, 0) : 0;
+        const int nl_dn = s_dn < a.npass ? max(a.bz_hi[s_dn] - a.bz_lo[s_dn] + 1, 0) : 0;
+        const int items_up = a.nup * nl_up * bxy, items_dn = (a.ndirs - a.nup) * nl_dn * bxy;
+        int item = j * 4 + w, rem;
+        if (item < items_up) {
+            d = item / (nl_up * bxy);
+            rem = item - d * (nl_up * bxy);
+            bz = a.bz_lo[s_up] + rem / bxy;
+            start = s_up;
+        } else {
+            item -= items_up;
+            if (item >= items_dn) return;
+            const int dd = item / (nl_dn * bxy);
+            rem = item - dd * (nl_dn * bxy);
+            d = a.nup + dd;
+            bz = a.bz_lo[s_dn] + rem / bxy;
+            start = s_dn;
+        }
+        const int bxyi = rem % bxy;
+        bx = bxyi % bm;
+        by = bxyi / bm;
+    } else {
+        d = x + 8 * (j / a.blocks_per_dir);
+        const int brick = (j % a.blocks_per_dir) * 4 + w;
+        if (d >= a.ndirs || brick >= a.nbricks) return;
+        bx = brick % bm;
+        by = (brick / bm) % bm;
+        bz = brick / (bm * bm);
+    }
     const int mx = bx * 4 + (l & 3), my = by * 4 + ((l >> 2) & 3), mz = bz * 4 + (l >> 4);
     if (mx >= M || my >= M || mz >= M) return;
     const float px = (float)mx * a.p_scale[0], py = (float)my * a.p_scale[1],
                 pz = (float)mz * a.p_scale[2];
+    if (a.xslab && min(a.npass - 1, (int)(pz / a.slab_h)) != start) return;  // the node starts in another slab
     const float tx = (float)(a.nx - 1), ty = (float)(a.ny - 1), tz = (float)(a.nz - 1);
     const int nx = a.nx, nxy = a.nx * a.ny;
     constexpr int elem = C == 3 ? 16 : 8;
@@ -1006,8 +1048,10 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = a.dpart[(int64_t)(d * C + c) * m3 + m];
     }
-    const bool up = u.z >= 0.0f, last = a.pass == a.npass - 1;
-    const int slab = up ? a.pass : a.npass - 1 - a.pass;
+    const bool up = u.z >= 0.0f;
+    // the slab marched in this pass; the edge slab takes every remaining sample
+    const int slab = a.xslab ? x : (up ? a.pass : a.npass - 1 - a.pass);
+    const bool last = a.xslab ? (up ? slab == a.npass - 1 : slab == 0) : a.pass == a.npass - 1;
     const float zlo = (float)slab * a.slab_h, zhi = (float)(slab + 1) * a.slab_h;
     // software pipeline: the corner loads of sample k + 1 are in flight
     // while sample k is accumulated (the positions do not depend on the sums)
@@ -1913,8 +1957,35 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     // slabs of about kScatSlabBytes of the packed volume each
     const int64_t plane = (int64_t)a.nx * a.ny * (C == 3 ? 16 : 8);
     const int planes = (int)std::max<int64_t>(1, kScatSlabBytes / plane);
-    a.npass = std::max(1, std::min(kScatMaxPasses, (a.nz - 1 + planes - 1) / planes));
-    a.slab_h = (float)((double)(a.nz - 1) / (double)a.npass);
+    // a volume larger than one slab: XCD x owns slab x of 8, so each XCD's
+    // L2 holds only its slab; a smaller volume is marched in one pass
+    a.xslab = plane * (a.nz - 1) > kScatSlabBytes ? 1 : 0;
+    a.nup = p->scat_nup;
+    if (a.xslab) {
+        a.npass = 8;
+        a.slab_h = (float)((double)(a.nz - 1) / (double)a.npass);
+        // brick layers (4 node planes each) of the nodes starting in each
+        // slab, widened by one layer each side (the kernel checks each node)
+        const int bmz = (a.M + 3) / 4;
+        for (int sl = 0; sl < 8; ++sl) {
+            a.bz_lo[sl] = bmz;
+            a.bz_hi[sl] = -1;
+        }
+        for (int mz = 0; mz < a.M; ++mz) {
+            const float pz = (float)mz * a.p_scale[2];
+            const int sl = std::min(a.npass - 1, (int)(pz / a.slab_h));
+            a.bz_lo[sl] = std::min(a.bz_lo[sl], mz / 4);
+            a.bz_hi[sl] = std::max(a.bz_hi[sl], mz / 4);
+        }
+        for (int sl = 0; sl < 8; ++sl)
+            if (a.bz_hi[sl] >= 0) {
+                a.bz_lo[sl] = std::max(0, a.bz_lo[sl] - 1);
+                a.bz_hi[sl] = std::min(bmz - 1, a.bz_hi[sl] + 1);
+            }
+    } else {
+        a.npass = std::max(1, std::min(kScatMaxPasses, (a.nz - 1 + planes - 1) / planes));
+        a.slab_h = (float)((double)(a.nz - 1) / (double)a.npass);
+    }
     const bool phase = scat_view_stride(p) != 0;
     if (phase) {
         a.cams = p->d_cams;
@@ -1928,8 +1999,23 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     }
     const dim3 rgrid((unsigned)blocks_for(m3), phase ? (unsigned)p->V : 1u);
     for (a.pass = 0; a.pass < a.npass; ++a.pass) {
-        if (C == 3) hipLaunchKernelGGL(inscatter_march_kernel<3>, dim3(nb), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(inscatter_march_kernel<1>, dim3(nb), dim3(kBlock), 0, s, a);
+        int nbp = nb;
+        if (a.xslab) {
+            // blocks per XCD: its up and down (direction, brick) items, 4 per block
+            const int bxy = ((a.M + 3) / 4) * ((a.M + 3) / 4);
+            int64_t most = 0;
+            for (int xx = 0; xx < 8; ++xx) {
+                const int su = xx - a.pass, sd = xx + a.pass;
+                const int64_t nu = su >= 0 ? std::max(a.bz_hi[su] - a.bz_lo[su] + 1, 0) : 0;
+                const int64_t ndn = sd < a.npass ? std::max(a.bz_hi[sd] - a.bz_lo[sd] + 1, 0) : 0;
+                const int64_t items = (int64_t)a.nup * nu * bxy + (int64_t)(a.ndirs - a.nup) * ndn * bxy;
+                most = std::max(most, (items + 3) / 4);
+            }
+            if (most == 0) continue;
+            nbp = (int)(8 * most);
+        }
+        if (C == 3) hipLaunchKernelGGL(inscatter_march_kernel<3>, dim3(nbp), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(inscatter_march_kernel<1>, dim3(nbp), dim3(kBlock), 0, s, a);
     }
     if (C == 3) {
         if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<3>, rgrid, dim3(kBlock), 0, s, a);
