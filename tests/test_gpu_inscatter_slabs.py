@@ -19,6 +19,8 @@ CASES = [
     (100, 80, 120, (-0.3, 0.1, 0.2), (0.9, 1.0, 1.6), 3, 11, 7, 0.0),
     (160, 160, 160, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 1, 16, 6, 0.0),
     (112, 112, 112, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 3, 12, 8, 0.5),
+    # flat: slabs a fraction of a voxel thick, samples skip several slabs
+    (512, 512, 4, (0.0, 0.0, 0.0), (1.0, 1.0, 0.03), 3, 4, 6, 0.0),
 ]
 
 
@@ -32,7 +34,16 @@ def test_slab_schedule_inscatter_matches_oracle(case):
     nx, ny, nz, lo, hi, C, M, dirs, g = CASES[case]
     assert nx * ny * (nz - 1) * (16 if C == 3 else 8) > 8 << 20  # beyond one slab
     grid = synth.Grid(nx, ny, nz, lo=lo, hi=hi)
-    em, sig = blob_volume(grid, C, 30 + case)
+    if nz >= 8:
+        em, sig = blob_volume(grid, C, 30 + case)
+    else:
+        # a flat box: smooth fields across it (blobs sized by its thickness would vanish)
+        x = np.linspace(0.0, 1.0, nx)[None, None, :]
+        y = np.linspace(0.0, 1.0, ny)[None, :, None]
+        z = np.linspace(0.0, 1.0, nz)[:, None, None]
+        em = np.stack([0.5 + 0.3 * np.sin(6 * x + c) * np.cos(5 * y) + 0.1 * z for c in range(C)])
+        sig = 5.0 + 3.0 * np.cos(4 * x + 3 * y) + 0 * z
+        em, sig = em.astype(np.float32), sig.astype(np.float32)
     rig = synth.ring_rig(3, 24, 20, seed=case)
     ref = oracle.inscatter(grid, as64(em), as64(sig), s_res=M, n_dirs=dirs, phase_g=g,
                            rig=rig if g != 0.0 else None)
