@@ -272,7 +272,8 @@ def main():
 
         def step_fn(x, k):
             em_p, sg_p = x[0].requires_grad_(True), x[1].requires_grad_(True)
-            opt = torch.optim.Adam([em_p, sg_p], lr=0.02)
+            # the fused form runs the whole update in one kernel per step
+            opt = torch.optim.Adam([em_p, sg_p], lr=0.02, fused=True)
             for _ in range(k):
                 opt.zero_grad(set_to_none=False)
                 loss = 0.5 * ((autograd.render(plan, em_p, sg_p, S) - frames) ** 2).sum()
