@@ -350,6 +350,19 @@ static void fib_dir(int d, int n, double u[3])
  * with n_dirs spherical-Fibonacci directions, segments of
  * s_step * (coarse node spacing) and the same segment rule as the render.
  * Single scattering: the march uses the emission only. */
+/* World position of in-scatter node (mx, my, mz): the M nodes per axis span
+ * the closed bounding box, node M-1 on the upper face. lo + (M-1) h can land
+ * an ulp past hi in FP64, which would put a face node outside the box and
+ * drop the rays that run along that face; the node is clamped into the box. */
+static void scat_node(const orc_grid *g, const double hs[3], int mx, int my, int mz, double p[3])
+{
+    const int m[3] = {mx, my, mz};
+    for (int a = 0; a < 3; ++a) {
+        const double v = g->lo[a] + m[a] * hs[a];
+        p[a] = v < g->lo[a] ? g->lo[a] : (v > g->hi[a] ? g->hi[a] : v);
+    }
+}
+
 int orc_inscatter(const orc_grid *g, int32_t C, const double *em, const double *sig, int32_t s_res,
                   int32_t n_dirs, double s_step, double *S)
 {
@@ -364,7 +377,8 @@ int orc_inscatter(const orc_grid *g, int32_t C, const double *em, const double *
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < M3; ++m) {
         int mx = (int)(m % s_res), my = (int)((m / s_res) % s_res), mz = (int)(m / ((long)s_res * s_res));
-        double p[3] = {g->lo[0] + mx * hs[0], g->lo[1] + my * hs[1], g->lo[2] + mz * hs[2]};
+        double p[3];
+        scat_node(g, hs, mx, my, mz, p);
         double acc[16];
         for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
         for (int dd = 0; dd < n_dirs; ++dd) {
@@ -435,7 +449,8 @@ int orc_inscatter_phase(const orc_grid *g, const orc_camera *cams, int32_t V, in
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < M3; ++m) {
         int mx = (int)(m % s_res), my = (int)((m / s_res) % s_res), mz = (int)(m / ((long)s_res * s_res));
-        double p[3] = {g->lo[0] + mx * hs[0], g->lo[1] + my * hs[1], g->lo[2] + mz * hs[2]};
+        double p[3];
+        scat_node(g, hs, mx, my, mz, p);
         double L[256][16];
         double U[256][3];
         for (int dd = 0; dd < n_dirs; ++dd) {

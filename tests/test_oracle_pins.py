@@ -298,6 +298,31 @@ def test_inscatter_constant_medium(sig):
     assert abs(S[0, 2, 2, 2] - ref_c) <= 1e-12 * ref_c
 
 
+def test_inscatter_constant_medium_on_the_box_faces():
+    """The in-scatter nodes span the closed box, the last node of each axis on
+    the face: the closed form holds at every node, including face nodes of a
+    box whose corner coordinates do not round evenly (lo + 3 h lands one ulp
+    past hi in FP64 here) and directions that run along a face (Fibonacci
+    direction 0 has no y component)."""
+    lo = (0.08756048, -0.72702558, -0.27326474)
+    hi = (1.24596599, 1.03268444, 0.9915425)
+    g = synth.Grid(11, 2, 11, lo=lo, hi=hi)
+    eps, sig, M, nd = 0.8, 1.3, 4, 8
+    S = oracle.inscatter(g, np.full((1, 11, 2, 11), eps), np.full((11, 2, 11), sig), s_res=M, n_dirs=nd)
+    dirs = fibonacci(nd)
+    assert dirs[0][1] == 0.0
+    lo_a, hi_a = np.array(lo), np.array(hi)
+    for mz in range(M):
+        for my in range(M):
+            for mx in range(M):
+                m = np.array([mx, my, mz])
+                p = np.where(m == M - 1, hi_a, lo_a + m * (hi_a - lo_a) / (M - 1))
+                ell = np.array([exit_length(p, u, lo_a, hi_a) for u in dirs])
+                ell = np.where(np.isfinite(ell), np.maximum(ell, 0.0), 0.0)
+                ref = (eps / sig * -np.expm1(-sig * ell)).mean()
+                assert abs(S[0, mz, my, mx] - ref) <= 1e-12 * max(ref, 1e-30), (mx, my, mz)
+
+
 # -------------------------------------------------------------- P8 Planck
 def test_planck_stefan_boltzmann_and_wien():
     sb = GOLD["stefan_boltzmann"]["value"]
