@@ -13,7 +13,8 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
   render               pinned (Beer-Lambert, sigma = 0 affine line integral,
                        fine-quadrature limit, 90-degree symmetry, point projection,
                        per-view in-scatter grids in a constant medium)
-  inscatter            pinned (closed form for constant fields, sigma = 0 limit)
+  inscatter            pinned (closed form for constant fields, also at every face node of an
+                       unevenly rounded box; sigma = 0 limit)
   inscatter (phase_g)  pinned (g = 0 reduces to the isotropic grid, sigma = 0
                        closed form, forward/backward brightening, |g| -> 1 limit)
   backproject_adjoint  pinned (adjoint identity, dense-matrix transpose)
