@@ -2,7 +2,7 @@
 shape (including fewer than 8 key points per axis), boxes off the unit cube,
 1-3 cameras anywhere outside or inside the box with random orientation and
 field of view, ragged images of 1-23 pixels per side, one or three channels.
-Render and adjoint back-projection through the C ABI against the FP64
+Render, adjoint back-projection and in-scatter grids through the C ABI against the FP64
 oracle at every generated case; three iterations of reconstruction (SART, EM
 or the paper's update; ordered subsets; in-scattering with or without the
 phase function; flame mask and visual hull) likewise."""
@@ -136,3 +136,36 @@ def test_random_reconstruction_matches_oracle(combo):
         if not same.any():
             return
     assert np.sqrt(np.mean((x - ref)[same] ** 2)) / scale <= 1e-3
+
+
+@st.composite
+def scatter_cases(draw):
+    base = list(draw(cases()))
+    base[8] = draw(st.sampled_from([1, 3]))
+    M = draw(st.integers(2, 9))
+    dirs = draw(st.integers(1, 24))
+    g = draw(st.sampled_from([0.0, 0.0, 0.7, -0.5]))
+    return base, M, dirs, g
+
+
+@settings(max_examples=60, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(scatter_cases())
+def test_random_inscatter_matches_oracle(sc):
+    """In-scatter grids (isotropic and Henyey-Greenstein) on random grids and
+    boxes, including face nodes of unevenly rounded boxes and directions that
+    run along a face."""
+    base, M, dirs, g = sc
+    grid, rig, em, sig = build(*base)
+    ref = oracle.inscatter(grid, as64(em), as64(sig), s_res=M, n_dirs=dirs, phase_g=g,
+                           rig=rig if g != 0.0 else None)
+    say("random in-scatter", base[:3], "C", base[8], "M", M, "dirs", dirs, "g", g, "seed", base[9])
+    with rte().Plan(grid, rig, channels=base[8], step_vox=0.5, albedo=0.3, scatter_res=M, scatter_dirs=dirs,
+                    phase_g=g) as p:
+        S = host(p.inscatter(dev(em), dev(sig)))
+    assert S.shape == ref.shape
+    scale = np.abs(ref).max()
+    if scale == 0.0:
+        assert np.abs(S).max() == 0.0
+    else:
+        assert np.abs(S - ref).max() <= RENDER_REL * scale
