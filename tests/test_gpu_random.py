@@ -2,7 +2,7 @@
 shape (including fewer than 8 key points per axis), boxes off the unit cube,
 1-3 cameras anywhere outside or inside the box with random orientation and
 field of view, ragged images of 1-23 pixels per side, one or three channels.
-Render, adjoint back-projection and in-scatter grids through the C ABI against the FP64
+Render, adjoint back-projection, in-scatter grids and render gradients through the C ABI against the FP64
 oracle at every generated case; three iterations of reconstruction (SART, EM
 or the paper's update; ordered subsets; in-scattering with or without the
 phase function; flame mask and visual hull) likewise."""
@@ -169,3 +169,43 @@ def test_random_inscatter_matches_oracle(sc):
         assert np.abs(S).max() == 0.0
     else:
         assert np.abs(S - ref).max() <= RENDER_REL * scale
+
+
+@st.composite
+def gradient_cases(draw):
+    base = list(draw(cases()))
+    scatter = draw(st.booleans())
+    if scatter:
+        base[8] = 3
+    return base, scatter, draw(st.sampled_from([0.0, 0.6]))
+
+
+@settings(max_examples=40, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(gradient_cases())
+def test_random_render_gradient_matches_oracle(gc):
+    """Gradients of a loss through the render (reverse march + gradient
+    gather) on random geometry, with and without in-scattering."""
+    base, scatter, g = gc
+    grid, rig, em, sig = build(*base)
+    C = em.shape[0]
+    M = 4 if scatter else 0
+    kw = dict(step_vox=0.5, albedo=0.3 if scatter else 0.0, background=0.05)
+    S = oracle.inscatter(grid, as64(em), as64(sig), s_res=4, n_dirs=6, phase_g=g,
+                         rig=rig if g != 0.0 else None) if scatter else None
+    y = f32(np.random.default_rng(base[9] + 3).normal(size=(rig.n_views, C, rig.height, rig.width)))
+    de_o, ds_o = oracle.render_grad(grid, rig, as64(em), as64(sig), as64(y), inscatter=S, **kw)
+    say("random gradient", base[:3], "views", base[5], "image", base[6:8], "C", C, "scatter", scatter, g,
+        "seed", base[9])
+    with rte().Plan(grid, rig, channels=C, scatter_res=M, scatter_dirs=6, phase_g=g if scatter else 0.0,
+                    gradients=True, **kw) as p:
+        Sd = None if S is None else dev(f32(S))
+        img, exit_T = p.render_forward(dev(em), dev(sig), Sd)
+        de, ds = p.render_backward(dev(em), dev(sig), Sd, exit_T, dev(y))
+        de, ds = host(de), host(ds)
+    for got, ref in ((de, de_o), (ds, ds_o)):
+        scale = np.abs(ref).max()
+        if scale == 0.0:
+            assert np.abs(got).max() == 0.0
+        else:
+            assert np.abs(got - ref).max() <= 1e-4 * scale
