@@ -915,16 +915,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
 
 // ----------------------------------------------------------- K2 in-scatter
 
-// In-scatter slab passes. A packed volume of at most kScatSlabBytes is
-// marched in one pass by all XCDs. A larger one is cut into 8 slabs along z
-// and XCD x marches slab x only, so its L2 (4 MB) holds one slab instead of
-// the volume: on the 128^3 colour workload (33 MB) the march takes 0.56 ms
+// In-scatter passes. A packed volume of at most kScatSlabBytes is marched in
+// one pass by all XCDs. A larger one is cut into 8 slabs along z and XCD x
+// marches slab x only, so its L2 (4 MB) holds one slab instead of the
+// volume: on the 128^3 colour workload (33 MB) the march takes 0.56 ms
 // instead of 0.82 ms with 4 slabs of 8 MB marched by all XCDs together; with
-// the same sample count, a 64^3 volume (4 MB) takes 0.29 ms in one pass.
-// (kScatMaxPasses bounds the passes of the older all-XCD slab form, which
-// the one-pass case still uses.)
+// the same sample count, a 64^3 volume (4 MB) takes 0.29 ms in one pass and
+// 0.37 ms in 8 slab passes.
 constexpr int64_t kScatSlabBytes = 8ll << 20;
-constexpr int kScatMaxPasses = 8;
 
 struct ScatArgs {
     const float *vol;
@@ -962,8 +960,8 @@ struct ScatArgs {
 //    monotone in z and cross one slab per pass, so in pass p XCD x takes the
 //    up-going rays of the nodes that start in slab x - p and the down-going
 //    rays of those starting in slab x + p; each XCD's working set is its slab.
-//  * otherwise: XCD x takes directions x, x + 8, ..., and pass p advances
-//    every ray through slab p (slab npass - 1 - p when it points down).
+//  * otherwise (one pass): XCD x takes directions x, x + 8, ... and every
+//    ray marches to the box exit (the one slab is the edge slab).
 // The march is software-pipelined: the corner loads of the next sample are
 // issued before the current sample is accumulated (the loads wait on memory,
 // the sums on nothing but the loads). Each (direction, node) sum is stored;
@@ -1954,9 +1952,7 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     const int C = p->params.channels;
     a.kstate = reinterpret_cast<int *>(a.dpart + (int64_t)a.ndirs * C * m3);
     a.tstate = a.dpart + (int64_t)a.ndirs * (C + 1) * m3;
-    // slabs of about kScatSlabBytes of the packed volume each
     const int64_t plane = (int64_t)a.nx * a.ny * (C == 3 ? 16 : 8);
-    const int planes = (int)std::max<int64_t>(1, kScatSlabBytes / plane);
     // a volume larger than one slab: XCD x owns slab x of 8, so each XCD's
     // L2 holds only its slab; a smaller volume is marched in one pass
     a.xslab = plane * (a.nz - 1) > kScatSlabBytes ? 1 : 0;
@@ -1983,8 +1979,8 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
                 a.bz_hi[sl] = std::min(bmz - 1, a.bz_hi[sl] + 1);
             }
     } else {
-        a.npass = std::max(1, std::min(kScatMaxPasses, (a.nz - 1 + planes - 1) / planes));
-        a.slab_h = (float)((double)(a.nz - 1) / (double)a.npass);
+        a.npass = 1;
+        a.slab_h = (float)(a.nz - 1);
     }
     const bool phase = scat_view_stride(p) != 0;
     if (phase) {
