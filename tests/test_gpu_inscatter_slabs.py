@@ -1,6 +1,7 @@
 """In-scatter grids of volumes larger than one slab (more than 8 MB packed),
 where each XCD marches its own z-slab of the volume and the rays cross one
-slab per pass: the grid must equal the FP64 oracle's one-march definition
+slab per pass until a final pass marches every ray still alive to its end:
+the grid must equal the FP64 oracle's one-march definition
 (Eq. 5 third term, Eq. 9) like the one-pass case of the smaller volumes."""
 import numpy as np
 import pytest
