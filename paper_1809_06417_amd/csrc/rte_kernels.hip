@@ -1125,20 +1125,24 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
     for (int c = 0; c < C; ++c) a.dpart[(int64_t)(d * C + c) * m3 + m] = acc[c];
 }
 
-// S_c(node) = (1 / ndirs) sum_d, the directions added in index order.
+// S_c(node) = (1 / ndirs) sum_d, the directions added in index order. Small
+// blocks: a 32^3 grid is 512 of them, enough to reach every CU.
+constexpr int kReduceBlock = 64;
 template <int C>
-__global__ __launch_bounds__(kBlock) void inscatter_reduce_kernel(ScatArgs a)
+__global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_kernel(ScatArgs a)
 {
     const int m3 = a.M * a.M * a.M;
-    const int m = blockIdx.x * kBlock + threadIdx.x;
+    const int m = blockIdx.x * kReduceBlock + threadIdx.x;
     if (m >= m3) return;
     float tot[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        tot[c] = 0.0f;
-        for (int d = 0; d < a.ndirs; ++d) tot[c] += a.dpart[(int64_t)(d * C + c) * m3 + m];
-        tot[c] *= a.inv_ndirs;
-    }
+    for (int c = 0; c < C; ++c) tot[c] = 0.0f;
+#pragma unroll 4
+    for (int d = 0; d < a.ndirs; ++d)
+#pragma unroll
+        for (int c = 0; c < C; ++c) tot[c] += a.dpart[(int64_t)(d * C + c) * m3 + m];
+#pragma unroll
+    for (int c = 0; c < C; ++c) tot[c] *= a.inv_ndirs;
     float4 o = make_float4(tot[0], 0.f, 0.f, 0.f);
     if constexpr (C == 3) {
         o.y = tot[1];
@@ -2002,6 +2006,7 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
         }
     }
     const dim3 rgrid((unsigned)blocks_for(m3), phase ? (unsigned)p->V : 1u);
+    const dim3 sgrid((unsigned)((m3 + kReduceBlock - 1) / kReduceBlock));
     for (a.pass = 0; a.pass < (a.xslab ? kScatFinalPass + 1 : a.npass); ++a.pass) {
         int nbp = nb;
         if (a.xslab) {
@@ -2023,10 +2028,10 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     }
     if (C == 3) {
         if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<3>, rgrid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(inscatter_reduce_kernel<3>, rgrid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(inscatter_reduce_kernel<3>, sgrid, dim3(kReduceBlock), 0, s, a);
     } else {
         if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<1>, rgrid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(inscatter_reduce_kernel<1>, rgrid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(inscatter_reduce_kernel<1>, sgrid, dim3(kReduceBlock), 0, s, a);
     }
     return hipGetLastError();
 }
