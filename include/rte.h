@@ -153,8 +153,10 @@ typedef struct {
  * temperatures evenly spaced over [t_min, t_max], the band radiances
  *   B_c(T) = int B(lambda, T) w_c(lambda) dlambda / int B(lambda, t_norm) w_ch(lambda) dlambda,
  * w_c a Gaussian band of centre band_nm[c] and standard deviation
- * band_std_nm, integrated by composite Simpson with `panels` panels over
- * +-6 standard deviations (built on the host in FP64). Extinction follows
+ * band_std_nm, over the window of +-6 standard deviations around the
+ * centre, integrated by composite 4-point Gauss-Legendre quadrature on
+ * panels / 4 sub-intervals (built on the host in FP64; every band's window
+ * must lie at positive wavelengths, else RTE_ERR_INVALID_ARG). Extinction follows
  * the soot load: sigma = sigma_max * max(0, (T - soot_t0) / soot_span).
  * `channel` is the fitted channel (1 = green, Sec. 3.3). */
 typedef struct {

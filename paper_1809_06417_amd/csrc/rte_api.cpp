@@ -344,7 +344,7 @@ int ensure_lut(rte_plan *p, const rte_temp_params *tp, hipStream_t s)
         return fail(RTE_ERR_INVALID_ARG, "temperature range invalid");
     if (!finite_pos(tp->band_std_nm)) return fail(RTE_ERR_INVALID_ARG, "band_std_nm must be > 0");
     for (int c = 0; c < 3; ++c)
-        if (!finite_pos(tp->band_nm[c]) || tp->band_nm[c] - 6.0f * tp->band_std_nm <= 0.0f)
+        if (!finite_pos(tp->band_nm[c]) || (double)tp->band_nm[c] - 6.0 * (double)tp->band_std_nm <= 0.0)
             return fail(RTE_ERR_INVALID_ARG, "band %d must lie at positive wavelengths", c);
     if (tp->channel < 0 || tp->channel > 2) return fail(RTE_ERR_INVALID_ARG, "channel must be 0, 1 or 2");
     if (!(tp->soot_span > 0.0f) || !std::isfinite(tp->sigma_max) || tp->sigma_max < 0.0f)
