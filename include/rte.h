@@ -228,28 +228,34 @@ int rte_ray_table(rte_plan *plan, float *t_near, float *t_far, int32_t *nseg, vo
 int rte_render(rte_plan *plan, const float *emission, const float *extinction,
                const float *inscatter, float *images, void *stream);
 
-/* rte_render that also writes the transmittance left at each ray's exit,
- * exit_transmittance [V][H][W] (what rte_render_backward needs to re-march
- * each ray backwards). */
+/* rte_render that also writes each ray's optical depth at its exit,
+ * exit_optical_depth [V][H][W] (FP64, tau_K = sum_k sigma_k Delta_k over the
+ * ray's samples, 0 for rays that miss the box; the exit transmittance is
+ * exp(-tau_K)). rte_render_backward re-marches each ray backwards from it.
+ * It is kept in FP64 rather than as the FP32 transmittance because
+ * exp(-tau_K) leaves the FP32 range (underflows) beyond tau_K of about 87,
+ * where the transmittance in front of the ray's first samples still
+ * matters. */
 int rte_render_forward(rte_plan *plan, const float *emission, const float *extinction,
-                       const float *inscatter, float *images, float *exit_transmittance,
+                       const float *inscatter, float *images, double *exit_optical_depth,
                        void *stream);
 
 /* Gradient of a scalar loss through the render of Eq. 5-8, given dL/dI.
  * For every ray a reverse march recovers the transmittance in front of each
- * sample from exit_transmittance (T_k = T_{k+1} e^{sigma_k Delta_k}; no
- * per-sample state is kept from the forward pass) and forms
+ * sample from exit_optical_depth (tau_k = tau_{k+1} - sigma_k Delta_k in
+ * FP64, T_k = exp(-tau_k); no per-sample state is kept from the forward
+ * pass) and forms
  *   dI_c/d eps_k   = T_k Delta_k phi_k,
  *   dI_c/d sigma_k = T_k (albedo S_c Delta_k phi_k + j_c Delta_k^2 phi'_k)
  *                    - Delta_k (radiance behind sample k);
  * these reach the key points through the trilinear weights in an
  * atomics-free voxel-owned gather. The in-scatter grid is held fixed.
  * Needs a plan created with RTE_PLAN_GRADIENTS. emission [C][nz][ny][nx],
- * extinction [nz][ny][nx], inscatter as in rte_render, exit_transmittance
+ * extinction [nz][ny][nx], inscatter as in rte_render, exit_optical_depth
  * from rte_render_forward on the same inputs, grad_images [V][C][H][W];
  * writes grad_emission [C][nz][ny][nx] and grad_extinction [nz][ny][nx]. */
 int rte_render_backward(rte_plan *plan, const float *emission, const float *extinction,
-                        const float *inscatter, const float *exit_transmittance,
+                        const float *inscatter, const double *exit_optical_depth,
                         const float *grad_images, float *grad_emission, float *grad_extinction,
                         void *stream);
 

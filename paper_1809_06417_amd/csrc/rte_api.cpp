@@ -630,11 +630,11 @@ int rte_render(rte_plan *plan, const float *emission, const float *extinction, c
 }
 
 int rte_render_forward(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
-                       float *images, float *exit_transmittance, void *stream)
+                       float *images, double *exit_optical_depth, void *stream)
 {
     if (int rc = check_plan(plan)) return rc;
-    if (!emission || !extinction || !images || !exit_transmittance)
-        return fail(RTE_ERR_INVALID_ARG, "null emission, extinction, images or exit transmittance");
+    if (!emission || !extinction || !images || !exit_optical_depth)
+        return fail(RTE_ERR_INVALID_ARG, "null emission, extinction, images or exit optical depth");
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
     const int C = plan->params.channels;
@@ -643,18 +643,18 @@ int rte_render_forward(rte_plan *plan, const float *emission, const float *extin
     if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
     RTE_LAUNCH(plan, RTE_KERNEL_RENDER, s,
                rte::launch_render(plan, C, true, scat, false, rte::kEpiImage, nullptr, C, 0, images, s,
-                                  exit_transmittance));
+                                  exit_optical_depth));
     return ok();
 }
 
 int rte_render_backward(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
-                        const float *exit_transmittance, const float *grad_images, float *grad_emission,
+                        const double *exit_optical_depth, const float *grad_images, float *grad_emission,
                         float *grad_extinction, void *stream)
 {
     if (int rc = check_plan(plan)) return rc;
     if (!(plan->params.flags & RTE_PLAN_GRADIENTS) || !plan->d_q)
         return fail(RTE_ERR_UNSUPPORTED, "plan was created without RTE_PLAN_GRADIENTS");
-    if (!emission || !extinction || !exit_transmittance || !grad_images || !grad_emission || !grad_extinction)
+    if (!emission || !extinction || !exit_optical_depth || !grad_images || !grad_emission || !grad_extinction)
         return fail(RTE_ERR_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     plan->last_stream = s;
@@ -662,7 +662,7 @@ int rte_render_backward(rte_plan *plan, const float *emission, const float *exti
     const bool scat = inscatter && plan->params.albedo > 0.0f && plan->params.scatter_res >= 2;
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack(plan, emission, extinction, C, s));
     if (scat) RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_scatter(plan, inscatter, s));
-    RTE_LAUNCH(plan, RTE_KERNEL_ADJOINT, s, rte::launch_adjoint_march(plan, scat, exit_transmittance, grad_images, s));
+    RTE_LAUNCH(plan, RTE_KERNEL_ADJOINT, s, rte::launch_adjoint_march(plan, scat, exit_optical_depth, grad_images, s));
     const float *dI = nullptr;
     RTE_LAUNCH(plan, RTE_KERNEL_PACK, s, rte::launch_pack_residual(plan, grad_images, &dI, s));
     RTE_LAUNCH(plan, RTE_KERNEL_GATHER, s, rte::launch_gather(plan, C, rte::kGatherGrad, dI, 0.f, 0.f, 0.f, s));

@@ -147,9 +147,9 @@ hipError_t launch_pack_residual(const rte_plan *p, const float *planar, const fl
 hipError_t launch_pack_scatter(const rte_plan *p, const float *planar, hipStream_t s);
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s, float *exit_T = nullptr,
+                         int frame_channel0, float *out, hipStream_t s, double *exit_tau = nullptr,
                          const float *mask = nullptr, float2 *err = nullptr, int sub_n = 1, int sub_s = 0);
-hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
+hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const double *exit_tau, const float *dI,
                                 hipStream_t s);
 hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,

@@ -573,7 +573,7 @@ struct RenderArgs {
     const float *frames;
     float *out;
     float *g;
-    float *exit_T;  // optional [V][H][W] transmittance at the exit (image renders)
+    double *exit_tau;  // optional [V][H][W] optical depth at the exit (image renders)
     const float *mask;   // optional [V][H][W] ray mask (1 adjust, 0 ignore) for residual epilogues
     float2 *err;         // optional per-slot (sum of squared residuals, count) over masked pixels
     int sub_n, sub_s;    // only views v with v % sub_n == sub_s (ordered subsets)
@@ -626,6 +626,9 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
 #pragma unroll
     for (int c = 0; c < C; ++c) I[c] = 0.0f;
     float T = 1.0f, Rsum = 0.0f;
+    // optical depth so far, in FP64: an image render hands it to the reverse
+    // march, which recovers every T_k from it even where T_K underflows
+    double tau = 0.0;
     float *gp = nullptr;
     if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
     ScatCorners scc;
@@ -686,8 +689,10 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
             for (int c = 0; c < C; ++c) em[c] = fmaf(as, S[c], em[c]);
         }
         float e;
-        const float ph = phi_exp(sig * len, e);
+        const float xo = sig * len;
+        const float ph = phi_exp(xo, e);
         const float wg = T * len * ph;
+        if constexpr (EPI == kEpiImage) tau += (double)xo;
         if constexpr (EMIS) {
 #pragma unroll
             for (int c = 0; c < C; ++c) I[c] = fmaf(wg, em[c], I[c]);
@@ -700,7 +705,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
         if (in_image) {
 #pragma unroll
             for (int c = 0; c < C; ++c) a.out[(v * C + c) * HW + pix] = fmaf(T, a.background, I[c]);
-            if (a.exit_T) a.exit_T[r] = T;
+            if (a.exit_tau) a.exit_tau[r] = tau;
         }
     } else if constexpr (EPI == kEpiSart || EPI == kEpiMlem || EPI == kEpiPaper) {
         const float m = !in_image ? 0.0f : (a.mask ? a.mask[r] : 1.0f);
@@ -781,7 +786,7 @@ struct GradArgs {
     const float *vol;
     const float4 *scat;
     int scat_vstride;     // as in RenderArgs
-    const float *exit_T;  // [V][H][W]
+    const double *exit_tau;  // [V][H][W] optical depth at the exit
     const float *dI;      // dL/dI [V][C][H][W]
     float2 *gq;           // per-sample outputs (g_k, q_k), [tile][K - 1 - k][lane]: row j = step j
     int W, H, tiles_x, tiles_per_view;
@@ -791,8 +796,11 @@ struct GradArgs {
 };
 
 // Reverse march of one pixel ray for the gradient of a loss with dL/dI given.
-// Starting from the stored exit transmittance T_K, each step recovers
-// T_k = T_{k+1} e^{a_k}, re-samples the volume, and writes
+// Starting from the stored exit optical depth tau_K = sum_k a_k (FP64), each
+// step takes a_k off it and recovers T_k = exp(-tau_k): a ray whose exit
+// transmittance underflows FP32 (tau_K beyond about 87) still gets the
+// exact T_k wherever T_k itself is representable. It re-samples the volume
+// and writes
 //   g_k = T_k Delta_k phi(a_k)                              (dI/d eps_k)
 //   q_k = sum_c dL/dI_c [T_k (albedo S_c Delta_k phi + j_c Delta_k^2 phi')
 //                        - Delta_k R_c]                      (dL/d sigma_k)
@@ -831,11 +839,12 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     int soff[8];
     corner_offsets(M, MM, 16, soff);
     float y[C], R[C];
-    float T = a.exit_T[r];
+    double tau = a.exit_tau[r];
+    const float TK = __expf(-(float)tau);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         y[c] = a.dI[(v * C + c) * HW + pix];
-        R[c] = T * a.background;
+        R[c] = TK * a.background;
     }
     float2 *gqp = a.gq + a.tile_off[tile] + lane;
     ScatCorners scc;
@@ -900,7 +909,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
         float e;
         const float ph = phi_exp(xo, e);
         const float dph = dphi_f(xo, e);
-        T = T * __expf(xo);  // transmittance in front of sample k
+        tau -= (double)xo;
+        const float T = __expf(-(float)tau);  // transmittance in front of sample k
         const float gk = T * len * ph;
         float qk = 0.0f;
 #pragma unroll
@@ -1889,12 +1899,12 @@ static hipError_t render_dispatch(const RenderArgs &a, bool emis, bool scat, boo
 }
 
 static RenderArgs render_args(const rte_plan *p, int epilogue, const float *frames, int frame_channels,
-                              int frame_channel0, float *out, float *exit_T, const float *mask, float2 *err)
+                              int frame_channel0, float *out, double *exit_tau, const float *mask, float2 *err)
 {
     RenderArgs a{};
     a.sub_n = 1;
     a.sub_s = 0;
-    a.exit_T = exit_T;
+    a.exit_tau = exit_tau;
     a.mask = mask;
     a.err = err;
     a.fC = frame_channels;
@@ -1934,10 +1944,10 @@ static RenderArgs render_args(const rte_plan *p, int epilogue, const float *fram
 
 hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, bool use_scatter,
                          bool write_g, int epilogue, const float *frames, int frame_channels,
-                         int frame_channel0, float *out, hipStream_t s, float *exit_T, const float *mask,
+                         int frame_channel0, float *out, hipStream_t s, double *exit_tau, const float *mask,
                          float2 *err, int sub_n, int sub_s)
 {
-    RenderArgs a = render_args(p, epilogue, frames, frame_channels, frame_channel0, out, exit_T, mask, err);
+    RenderArgs a = render_args(p, epilogue, frames, frame_channels, frame_channel0, out, exit_tau, mask, err);
     a.sub_n = sub_n;
     a.sub_s = sub_s;
     if (channels == 3) return render_dispatch<3>(a, use_emission, use_scatter, write_g, epilogue, s);
@@ -2047,7 +2057,7 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float *exit_T, const float *dI,
+hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const double *exit_tau, const float *dI,
                                 hipStream_t s)
 {
     GradArgs a{};
@@ -2059,7 +2069,7 @@ hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const float
     a.vol = p->d_vol;
     a.scat = p->d_scat;
     a.scat_vstride = scat_view_stride(p);
-    a.exit_T = exit_T;
+    a.exit_tau = exit_tau;
     a.dI = dI;
     a.gq = reinterpret_cast<float2 *>(p->d_q);
     a.W = p->W;

@@ -74,7 +74,8 @@ def leave_one_view_out(grid, rig, emission, extinction, test_view, iters, *, ste
     from the result. Returns a dict with per-channel errors: 'input' (mean
     over the input views), 'test', 'volume' (inside the visual hull of the
     input views' flame masks), plus the seconds spent reconstructing, the
-    march samples per iteration and (timing=True) per-kernel (ms, launches)
+    march samples and hit rays per iteration and (timing=True) per-kernel
+    (ms, launches)
     of the reconstruction."""
     import torch
     C = emission.shape[0]
@@ -95,7 +96,7 @@ def leave_one_view_out(grid, rig, emission, extinction, test_view, iters, *, ste
         seconds = time.perf_counter() - t0
         kernels = {k: sub.kernel_time(k) for k in rte.KERNELS} if timing else {}
         sub.set_timing(False)
-        samples = sub.samples
+        samples, hit_rays = sub.samples, sub.hit_rays
         Sx = full.inscatter(x, extinction) if albedo > 0 else None
         I = full.render(x, extinction, Sx)
         inside = sub.visual_hull(sub.flame_mask(Fin, thr))
@@ -106,7 +107,7 @@ def leave_one_view_out(grid, rig, emission, extinction, test_view, iters, *, ste
     return {"input": err[inputs].mean(axis=0), "test": err[test_view],
             "volume": volume_rmse(xh, em_h, inside_h, 255.0 / max(float(em_h.max()), 1e-30)),
             "reconstruct_s": seconds, "iters": iters, "test_view": test_view, "samples_per_iter": samples,
-            "kernels": kernels}
+            "hit_rays": hit_rays, "kernels": kernels}
 
 
 def camera_sweep(grid, temperature, rigs, iters, *, temp=None, flame_frac=0.01, observable=1e-3):

@@ -175,14 +175,17 @@ def _stream():
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t, shape=None, name="tensor"):
-    """Device pointer of a float32/int32 contiguous GPU tensor (None -> NULL)."""
+def _ptr(t, shape=None, name="tensor", fp64=False):
+    """Device pointer of a float32/int32 (float64 with fp64=True) contiguous
+    GPU tensor (None -> NULL)."""
     if t is None:
         return None
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a GPU torch tensor")
-    if t.dtype not in (torch.float32, torch.int32):
+    if fp64 and t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64 (got {t.dtype})")
+    if not fp64 and t.dtype not in (torch.float32, torch.int32):
         raise TypeError(f"{name} must be float32 (got {t.dtype})")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
@@ -265,17 +268,19 @@ class Plan:
         return out
 
     def render_forward(self, emission, extinction, inscatter=None):
-        """Images and the exit transmittance of every ray (for render_backward)."""
+        """Images and the FP64 exit optical depth of every ray (for
+        render_backward; the exit transmittance is exp(-depth))."""
+        import torch
         C, M = self.channels, self.scatter_res
         out = self._new(self.img_shape())
-        exit_T = self._new((self.V, self.H, self.W))
+        exit_tau = self._new((self.V, self.H, self.W), torch.float64)
         _check(lib().rte_render_forward(self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
                                         _ptr(extinction, self.vol_shape, "extinction"),
                                         _ptr(inscatter, self.scat_shape, "inscatter"),
-                                        _ptr(out), _ptr(exit_T), _stream()))
-        return out, exit_T
+                                        _ptr(out), _ptr(exit_tau, fp64=True), _stream()))
+        return out, exit_tau
 
-    def render_backward(self, emission, extinction, inscatter, exit_T, grad_images):
+    def render_backward(self, emission, extinction, inscatter, exit_tau, grad_images):
         """(dL/d emission, dL/d extinction) given dL/d images."""
         C, M = self.channels, self.scatter_res
         g_em = self._new((C,) + self.vol_shape)
@@ -283,7 +288,7 @@ class Plan:
         _check(lib().rte_render_backward(
             self._h, _ptr(emission, (C,) + self.vol_shape, "emission"),
             _ptr(extinction, self.vol_shape, "extinction"), _ptr(inscatter, self.scat_shape, "inscatter"),
-            _ptr(exit_T, (self.V, self.H, self.W), "exit_T"),
+            _ptr(exit_tau, (self.V, self.H, self.W), "exit_tau", fp64=True),
             _ptr(grad_images, self.img_shape(), "grad_images"), _ptr(g_em), _ptr(g_sig), _stream()))
         return g_em, g_sig
 

@@ -36,8 +36,39 @@ def test_render_gradient_matches_oracle(name):
                     background=c["bg"], scatter_res=c.get("M", 0), scatter_dirs=c.get("dirs", 32),
                     gradients=True) as p:
         Sd = None if S is None else dev(S)
-        img, exit_T = p.render_forward(dev(c["em"]), dev(sig), Sd)
-        de, ds = p.render_backward(dev(c["em"]), dev(sig), Sd, exit_T, dev(y))
+        img, exit_tau = p.render_forward(dev(c["em"]), dev(sig), Sd)
+        de, ds = p.render_backward(dev(c["em"]), dev(sig), Sd, exit_tau, dev(y))
+        de, ds = host(de), host(ds)
+    assert rel_max(de, de_o) <= GRAD_REL
+    assert rel_max(ds, ds_o) <= GRAD_REL
+
+
+def test_render_gradient_deep_optical_depth():
+    """Rays whose exit transmittance underflows FP32 (optical depth up to
+    ~180, exp(-180) ~ 1e-78): the reverse march recovers T_k from the FP64
+    exit optical depth, so the front samples of those rays still carry their
+    gradient (Eq. 6 recomputed in reverse)."""
+    g = synth.Grid(20, 20, 20)
+    rig = synth.ring_rig(3, 24, 20, elevation_jitter_deg=10, seed=4)
+    centres = [np.array([0.5, 0.5, 0.5]), np.array([0.4, 0.6, 0.45])]
+    covs = [np.diag([0.12 ** 2] * 3), np.diag([0.08 ** 2, 0.1 ** 2, 0.09 ** 2])]
+    peaks = np.array([[0.8, 0.6, 0.3, 500.0], [0.5, 0.9, 0.4, 300.0]])
+    f = synth.blob_fields(g, centres, covs, peaks)
+    em, sig = f32(f[:3]), f32(f[3] + 0.05)
+    tau = oracle.render(g, rig, as64(sig)[None], np.zeros_like(as64(sig)), step_vox=STEP)
+    assert tau.max() >= 150.0  # exit transmittance below FP32's smallest denormal
+    S = f32(oracle.inscatter(g, as64(em), as64(sig), s_res=8, n_dirs=16))
+    kw = dict(step_vox=STEP, albedo=0.3, background=0.05, inscatter=as64(S))
+    I = oracle.render(g, rig, as64(em), as64(sig), **kw)
+    F = np.random.default_rng(8).uniform(0.0, 0.5, size=I.shape)
+    y = f32(I - F)
+    de_o, ds_o = oracle.render_grad(g, rig, as64(em), as64(sig), as64(y), **kw)
+    say("render gradient, optical depth", f"{tau.max():.0f}")
+    with rte().Plan(g, rig, channels=3, step_vox=STEP, albedo=0.3, background=0.05, scatter_res=8,
+                    scatter_dirs=16, gradients=True) as p:
+        img, exit_tau = p.render_forward(dev(em), dev(sig), dev(S))
+        np.testing.assert_allclose(host(exit_tau), tau[:, 0], rtol=1e-5, atol=1e-6)
+        de, ds = p.render_backward(dev(em), dev(sig), dev(S), exit_tau, dev(y))
         de, ds = host(de), host(ds)
     assert rel_max(de, de_o) <= GRAD_REL
     assert rel_max(ds, ds_o) <= GRAD_REL
@@ -57,8 +88,8 @@ def test_autograd_function_matches_backward_and_finite_differences():
         loss = 0.5 * ((autograd.render(p, em, sig, S) - F) ** 2).sum()
         loss.backward()
         with torch.no_grad():
-            img, exit_T = p.render_forward(em.detach(), sig.detach(), S)
-            de, ds = p.render_backward(em.detach(), sig.detach(), S, exit_T, (img - F).contiguous())
+            img, exit_tau = p.render_forward(em.detach(), sig.detach(), S)
+            de, ds = p.render_backward(em.detach(), sig.detach(), S, exit_tau, (img - F).contiguous())
         assert torch.equal(em.grad, de) and torch.equal(sig.grad, ds)
 
         def L(e, s):
@@ -111,8 +142,8 @@ def test_full_size_gradient_against_finite_differences():
         F = p.render(emg, sgg, S)
         em = (emg * 0.8).contiguous()
         sig = (sgg * 0.9 + 0.02).contiguous()
-        img, exit_T = p.render_forward(em, sig, S)
-        de, ds = p.render_backward(em, sig, S, exit_T, (img - F).contiguous())
+        img, exit_tau = p.render_forward(em, sig, S)
+        de, ds = p.render_backward(em, sig, S, exit_tau, (img - F).contiguous())
 
         def L(e, s):
             return 0.5 * ((p.render(e, s, S) - F).double() ** 2).sum().item()
@@ -167,9 +198,9 @@ def test_full_size_gradient_matches_oracle_on_two_views():
         F = p.render(emg, sgg, S)
         em = f32(em_gt * 0.8)
         sig = f32(sig_gt * 0.9 + 0.02)
-        img, exit_T = p.render_forward(dev(em), dev(sig), S)
+        img, exit_tau = p.render_forward(dev(em), dev(sig), S)
         y = host((img - F).contiguous())
-        de, ds = p.render_backward(dev(em), dev(sig), S, exit_T, dev(y))
+        de, ds = p.render_backward(dev(em), dev(sig), S, exit_tau, dev(y))
         de, ds, S = host(de), host(ds), host(S)
     de_o, ds_o = oracle.render_grad(g, rig, as64(em), as64(sig), y, step_vox=STEP, albedo=0.3,
                                     inscatter=S)

@@ -82,8 +82,8 @@ def test_phase_gradient_matches_oracle():
     de_o, ds_o = oracle.render_grad(c["g"], c["rig"], as64(c["em"]), as64(sig), as64(y), **kw)
     say("phase gradient")
     with hg_plan(c, -0.4, gradients=True) as p:
-        img, exit_T = p.render_forward(dev(c["em"]), dev(sig), dev(S))
-        de, ds = p.render_backward(dev(c["em"]), dev(sig), dev(S), exit_T, dev(y))
+        img, exit_tau = p.render_forward(dev(c["em"]), dev(sig), dev(S))
+        de, ds = p.render_backward(dev(c["em"]), dev(sig), dev(S), exit_tau, dev(y))
         de, ds = host(de), host(ds)
     assert rel_max(de, de_o) <= GRAD_REL
     assert rel_max(ds, ds_o) <= GRAD_REL

@@ -200,8 +200,8 @@ def test_random_render_gradient_matches_oracle(gc):
     with rte().Plan(grid, rig, channels=C, scatter_res=M, scatter_dirs=6, phase_g=g if scatter else 0.0,
                     gradients=True, **kw) as p:
         Sd = None if S is None else dev(f32(S))
-        img, exit_T = p.render_forward(dev(em), dev(sig), Sd)
-        de, ds = p.render_backward(dev(em), dev(sig), Sd, exit_T, dev(y))
+        img, exit_tau = p.render_forward(dev(em), dev(sig), Sd)
+        de, ds = p.render_backward(dev(em), dev(sig), Sd, exit_tau, dev(y))
         de, ds = host(de), host(ds)
     for got, ref in ((de, de_o), (ds, ds_o)):
         scale = np.abs(ref).max()
