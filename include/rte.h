@@ -228,6 +228,34 @@ int rte_ray_table(rte_plan *plan, float *t_near, float *t_far, int32_t *nseg, vo
 int rte_render(rte_plan *plan, const float *emission, const float *extinction,
                const float *inscatter, float *images, void *stream);
 
+/* rte_render without a plan, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. It gives the images rte_render gives on a plan created from the
+ * same grid, cameras and params (the same kernels, bitwise the same result),
+ * and allocates nothing: the camera copy, ray table, tile list, packed
+ * volume and packed in-scatter grid live in one device array of
+ * RTE_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends. The first call on a device looks up the array's
+ * address there (make it outside graph capture); every call then only
+ * enqueues kernels on `stream` (the cameras travel in kernel arguments).
+ * Limits: at most RTE_STATIC_MAX_VIEWS cameras (RTE_ERR_UNSUPPORTED), and the
+ * workspaces, each rounded up to 256 bytes, must fit the array
+ * (RTE_ERR_BUDGET): 136 V + 36 V W H + 4 V ceil(W/8) ceil(H/8)
+ * + (16 for 3 channels, 8 for 1) nx ny nz + 16 M^3 (times V when
+ * phase_g != 0; 0 without in-scattering) bytes -- e.g. a 128^3 RGB volume
+ * seen by 8 views of 512x512 with a 32^3 in-scatter grid takes 110 MB.
+ * Nothing is enqueued after an error. All calls on one GPU share the array
+ * and each call overwrites it: calls that may overlap on one GPU (other
+ * streams, other host threads) race, and the caller must order them.
+ * Arguments: grid, cams, ncams and params as for rte_plan_create
+ * (params->flags is ignored); emission, extinction, inscatter and images as
+ * for rte_render. */
+#define RTE_STATIC_SCRATCH_BYTES (128u << 20)
+#define RTE_STATIC_MAX_VIEWS 16
+int rte_render_static(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                      const rte_render_params *params, const float *emission, const float *extinction,
+                      const float *inscatter, float *images, void *stream);
+
 /* rte_render that also writes each ray's optical depth at its exit,
  * exit_optical_depth [V][H][W] (FP64, tau_K = sum_k sigma_k Delta_k over the
  * ray's samples, 0 for rays that miss the box; the exit transmittance is

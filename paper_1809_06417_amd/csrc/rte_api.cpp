@@ -629,6 +629,49 @@ int rte_render(rte_plan *plan, const float *emission, const float *extinction, c
     return ok();
 }
 
+int rte_render_static(const rte_grid *grid, const rte_camera *cams, int32_t ncams,
+                      const rte_render_params *params, const float *emission, const float *extinction,
+                      const float *inscatter, float *images, void *stream)
+{
+    int rc = validate_config(grid, cams, ncams, params);
+    if (rc) return rc;
+    if (!emission || !extinction || !images) return fail(RTE_ERR_INVALID_ARG, "null emission, extinction or images");
+    if (ncams > rte::kStaticMaxViews)
+        return fail(RTE_ERR_UNSUPPORTED, "rte_render_static takes at most %d cameras (got %d)",
+                    rte::kStaticMaxViews, ncams);
+    const Derived d = derive(grid, cams, ncams, params);
+    const int M = params->scatter_res >= 2 ? params->scatter_res : 0;
+    const rte::StaticLayout L =
+        rte::static_layout(d.V, d.W, d.H, d.n_nodes, params->channels, M, params->phase_g != 0.0f);
+    if (L.total > rte::kStaticScratchBytes)
+        return fail(RTE_ERR_BUDGET,
+                    "rte_render_static needs %zu bytes of workspace; its static device array holds %zu "
+                    "(use a plan: rte_plan_create + rte_render)",
+                    L.total, rte::kStaticScratchBytes);
+    // a plan that owns nothing: its configuration, with workspace pointers
+    // that the launcher sets into the static array
+    rte_plan view;
+    view.grid = *grid;
+    view.params = *params;
+    view.V = d.V;
+    view.W = d.W;
+    view.H = d.H;
+    view.tiles_x = d.tiles_x;
+    view.tiles_y = d.tiles_y;
+    view.tiles_per_view = d.tiles_per_view;
+    view.n_tiles = d.n_tiles;
+    view.n_rays = d.n_rays;
+    view.n_nodes = d.n_nodes;
+    view.n_cells = d.n_cells;
+    view.n_part_cells = d.n_part_cells;
+    for (int i = 0; i < 3; ++i) view.h[i] = d.h[i];
+    view.ds = d.ds;
+    const hipError_t e = rte::launch_render_static(&view, cams, emission, extinction, inscatter, images,
+                                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(RTE_ERR_HIP, "rte_render_static launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
 int rte_render_forward(rte_plan *plan, const float *emission, const float *extinction, const float *inscatter,
                        float *images, double *exit_optical_depth, void *stream)
 {

@@ -18,6 +18,12 @@ namespace rte {
 constexpr int kTile = 8;
 constexpr int kTileRays = kTile * kTile;
 
+// Plan-free render (rte_render_static): its workspaces live in one static
+// device array of kStaticScratchBytes per GPU; at most kStaticMaxViews
+// cameras, which travel in the kernel arguments.
+constexpr size_t kStaticScratchBytes = RTE_STATIC_SCRATCH_BYTES;
+constexpr int kStaticMaxViews = RTE_STATIC_MAX_VIEWS;
+
 // Back-projection / epilogue selectors shared by launch wrappers and kernels.
 enum ResidualMode : int {
     kEpiImage = 0,  // write I_c
@@ -172,6 +178,20 @@ hipError_t launch_temp_map(const rte_plan *p, const float *T, float *em_planar, 
                            hipStream_t s);
 hipError_t launch_temp_invert(const rte_plan *p, const float *e, float *T, int lut_size,
                               int fit_channel, float t_min, float t_max, hipStream_t s);
+
+// ---- plan-free render over the static device array ----
+// Byte offsets of its workspaces in the array (each 256-byte aligned).
+struct StaticLayout {
+    size_t cams, rayA, rayB, tnear, order, vol, scat, total;
+};
+StaticLayout static_layout(int V, int W, int H, int64_t n_nodes, int C, int M, bool per_view_scatter);
+// Address of this device's array (looked up once per device).
+hipError_t static_scratch(void **addr);
+// Ray table, tile list, packing and image render of `view` (a plan whose
+// configuration fields are set and whose workspace pointers this call points
+// into the array) on stream s.
+hipError_t launch_render_static(rte_plan *view, const rte_camera *cams, const float *emission,
+                                const float *extinction, const float *inscatter, float *images, hipStream_t s);
 
 // ---- host LUT builder (rte_lut.cpp) ----
 void build_temperature_lut(const rte_temp_params &tp, std::vector<float> &lut);

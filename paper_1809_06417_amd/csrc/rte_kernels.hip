@@ -20,6 +20,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "rte_internal.h"
@@ -1761,6 +1762,27 @@ __global__ __launch_bounds__(kBlock) void err_reduce_kernel(const float2 *err, i
 
 static inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// Cameras of a plan-free render, passed by value in the kernel arguments
+// (nothing is copied from host memory at run time) and stored for the ray
+// table kernel.
+struct StaticCams {
+    rte_camera cam[kStaticMaxViews];
+    int n;
+};
+
+__global__ __launch_bounds__(64) void cams_store_kernel(StaticCams c, rte_camera *out)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) out[i] = c.cam[i];
+}
+
+// Launch order of a plan-free render: every tile in index order.
+__global__ __launch_bounds__(kBlock) void iota_kernel(int32_t *out, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = i;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host launches
@@ -2388,6 +2410,106 @@ hipError_t launch_step_batch(rte_plan *const *plans, int n, hipStream_t s, hipEv
     if (C == 3) { RTE_STEP(3) }
     RTE_STEP(1)
 #undef RTE_STEP
+}
+
+}  // namespace rte
+
+// ---------------------------------------------- render without a plan
+
+// Workspace of rte_render_static: one array per GPU, held until the process
+// ends. Host code never passes `scratch` itself to a kernel (on the host it is
+// only a stand-in for the symbol): each device's address is looked up once
+// with hipGetSymbolAddress and kernels receive that address.
+static __device__ __align__(256) unsigned char scratch[rte::kStaticScratchBytes];
+
+namespace rte {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+hipError_t static_scratch(void **addr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+StaticLayout static_layout(int V, int W, int H, int64_t n_nodes, int C, int M, bool per_view_scatter)
+{
+    StaticLayout L{};
+    const int64_t rays = (int64_t)V * W * H;
+    const int64_t tiles = (int64_t)V * ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t here = at;
+        at += align256(bytes);
+        return here;
+    };
+    L.cams = take(sizeof(rte_camera) * (size_t)V);
+    L.rayA = take(sizeof(float4) * (size_t)rays);
+    L.rayB = take(sizeof(float4) * (size_t)rays);
+    L.tnear = take(sizeof(float) * (size_t)rays);
+    L.order = take(sizeof(int32_t) * (size_t)tiles);
+    L.vol = take((C == 3 ? 16 : 8) * (size_t)n_nodes);
+    const size_t grids = per_view_scatter ? (size_t)V : 1;
+    L.scat = take(M >= 2 ? sizeof(float4) * grids * (size_t)M * M * M : 0);
+    L.total = at;
+    return L;
+}
+
+hipError_t launch_render_static(rte_plan *view, const rte_camera *cams, const float *emission,
+                                const float *extinction, const float *inscatter, float *images, hipStream_t s)
+{
+    void *base = nullptr;
+    hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) return e;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    const rte_render_params &pr = view->params;
+    const int C = pr.channels;
+    const int M = pr.scatter_res >= 2 ? pr.scatter_res : 0;
+    const StaticLayout L = static_layout(view->V, view->W, view->H, view->n_nodes, C, M, pr.phase_g != 0.0f);
+    if (L.total > kStaticScratchBytes) return hipErrorOutOfMemory;
+    if (view->V > kStaticMaxViews) return hipErrorInvalidValue;
+    view->d_cams = reinterpret_cast<rte_camera *>(b + L.cams);
+    view->d_rayA = reinterpret_cast<float4 *>(b + L.rayA);
+    view->d_rayB = reinterpret_cast<float4 *>(b + L.rayB);
+    view->d_tnear = reinterpret_cast<float *>(b + L.tnear);
+    view->d_tile_order = reinterpret_cast<int32_t *>(b + L.order);
+    view->d_vol = reinterpret_cast<float *>(b + L.vol);
+    view->d_scat = M ? reinterpret_cast<float4 *>(b + L.scat) : nullptr;
+    view->n_active_tiles = view->n_tiles;
+    // every byte the render reads is written earlier in this call: nothing
+    // in the array has to start at zero
+    StaticCams sc{};
+    for (int v = 0; v < view->V; ++v) sc.cam[v] = cams[v];
+    sc.n = view->V;
+    hipLaunchKernelGGL(cams_store_kernel, dim3(1), dim3(64), 0, s, sc, view->d_cams);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_ray_table(view, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(view->n_tiles)), dim3(kBlock), 0, s, view->d_tile_order,
+                       view->n_tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_pack(view, emission, extinction, C, s)) != hipSuccess) return e;
+    const bool scat = inscatter && pr.albedo > 0.0f && M;
+    if (scat && (e = launch_pack_scatter(view, inscatter, s)) != hipSuccess) return e;
+    return launch_render(view, C, true, scat, false, kEpiImage, nullptr, C, 0, images, s);
 }
 
 }  // namespace rte

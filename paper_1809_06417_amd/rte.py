@@ -15,7 +15,8 @@ import numpy as np
 __all__ = [
     "LIB_PATH", "lib", "RteError", "Plan", "TempParams", "plan_create", "render", "inscatter",
     "backproject", "reconstruct", "reconstruct_temperature", "temperature_map",
-    "temperature_invert", "KERNELS", "UPDATES", "job_step", "suggest_grid",
+    "temperature_invert", "KERNELS", "UPDATES", "job_step", "suggest_grid", "render_static",
+    "STATIC_SCRATCH_BYTES", "STATIC_MAX_VIEWS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
@@ -24,6 +25,7 @@ RTE_OK, RTE_ERR_INVALID_ARG, RTE_ERR_BUDGET, RTE_ERR_HIP, RTE_ERR_UNSUPPORTED = 
 KERNELS = {"rays": 0, "render": 1, "inscatter": 2, "gather": 3, "update": 4, "temp_map": 5,
            "pack": 6, "weights": 7, "colsum": 8, "adjoint": 9}
 RTE_PLAN_GRADIENTS = 1
+STATIC_SCRATCH_BYTES, STATIC_MAX_VIEWS = 128 << 20, 16  # RTE_STATIC_SCRATCH_BYTES, RTE_STATIC_MAX_VIEWS
 UPDATES = {"sart": 0, "paper": 1, "mlem": 2}
 BP_MODES = {"adjoint": 0, "paper": 1}
 
@@ -111,6 +113,7 @@ def lib():
     L.rte_plan_counts.argtypes = [vp, P(ct.c_uint64), P(ct.c_uint64)]
     L.rte_ray_table.argtypes = [vp, vp, vp, vp, vp]
     L.rte_render.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.rte_render_static.argtypes = [P(Grid), P(Camera), i32, P(RenderParams), vp, vp, vp, vp, vp]
     L.rte_render_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.rte_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.rte_inscatter.argtypes = [vp, vp, vp, vp, vp]
@@ -449,6 +452,29 @@ def job_step(plans):
     """One iteration for every plan with an open job, batched in one launch per phase."""
     arr = (ct.c_void_p * len(plans))(*[p._h for p in plans])
     _check(lib().rte_job_step(arr, len(plans), _stream()))
+
+
+def render_static(grid, rig, emission, extinction, inscatter=None, channels=1, step_vox=0.5, albedo=0.0,
+                  background=0.0, scatter_res=0, scatter_dirs=32, scatter_step=0.5, phase_g=0.0, out=None):
+    """Images [V, C, H, W] of rte_render_static: the render of a plan built from
+    these arguments, without a plan (the library's static device array holds
+    the workspaces; nothing is allocated on the device by the call). `out`
+    may be given to keep the call free of torch allocations too."""
+    import torch
+    cams, V = _cams(rig)
+    p = _params(channels, step_vox, albedo, background, scatter_res, scatter_dirs, scatter_step, 0, phase_g)
+    vol = (int(grid.nz), int(grid.ny), int(grid.nx))
+    C, H, W = int(channels), int(rig.height), int(rig.width)
+    M = int(scatter_res)
+    scat_shape = ((V,) if phase_g != 0.0 and M >= 2 else ()) + (C, M, M, M)
+    if out is None:
+        torch.cuda.init()
+        out = torch.empty((V, C, H, W), device="cuda", dtype=torch.float32)
+    _check(lib().rte_render_static(ct.byref(_grid(grid)), cams, V, ct.byref(p),
+                                   _ptr(emission, (C,) + vol, "emission"), _ptr(extinction, vol, "extinction"),
+                                   _ptr(inscatter, scat_shape, "inscatter"), _ptr(out, (V, C, H, W), "images"),
+                                   _stream()))
+    return out
 
 
 # Functional aliases with the ABI's names.

@@ -140,3 +140,24 @@ def test_suggest_grid_matches_oracle_and_rejects_bad_input():
     assert L.rte_suggest_grid(cams, 0, lo, hi, 1.5, ct.byref(g), None) == rte.RTE_ERR_INVALID_ARG
     assert L.rte_suggest_grid(cams, V, hi, lo, 1.5, ct.byref(g), None) == rte.RTE_ERR_INVALID_ARG
     assert g.nx == 0
+
+
+def test_static_render_rejects_oversize_and_too_many_views():
+    """rte_render_static checks its limits on the host before anything is
+    enqueued: workspaces beyond the static device array give RTE_ERR_BUDGET,
+    more cameras than its kernel arguments carry RTE_ERR_UNSUPPORTED (the
+    array pointers below are never dereferenced)."""
+    L = rte.lib()
+    g = rte._grid(synth.Grid(64, 64, 64))
+    p = rte._params(3, 0.5, 0.0, 0.0, 0, 32, 0.5)
+    fake = ct.c_void_p(256)
+    cams, V = rte._cams(synth.ring_rig(16, 1024, 1024))  # 36 B per ray: 604 MB of ray table
+    rc = L.rte_render_static(ct.byref(g), cams, V, ct.byref(p), fake, fake, None, fake, None)
+    assert rc == rte.RTE_ERR_BUDGET
+    assert "static device array" in L.rte_last_error().decode()
+    cams, V = rte._cams(synth.ring_rig(rte.STATIC_MAX_VIEWS + 1, 8, 8))
+    rc = L.rte_render_static(ct.byref(g), cams, V, ct.byref(p), fake, fake, None, fake, None)
+    assert rc == rte.RTE_ERR_UNSUPPORTED
+    cams, V = rte._cams(synth.ring_rig(4, 8, 8))
+    rc = L.rte_render_static(ct.byref(g), cams, V, ct.byref(p), fake, None, None, fake, None)
+    assert rc == rte.RTE_ERR_INVALID_ARG
