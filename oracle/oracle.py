@@ -19,7 +19,8 @@ __all__ = [
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# RTE_SANITIZE=1: the AddressSanitizer/UBSan build (python -m oracle.build --sanitize)
+_LIB_PATH = os.path.join(_HERE, "liboracle.asan.so" if os.environ.get("RTE_SANITIZE") == "1" else "liboracle.so")
 _lib = None
 
 
@@ -53,7 +54,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             from . import build as _b
-            _b.build()
+            _b.build(sanitize=_LIB_PATH.endswith(".asan.so"))
         _lib = ct.CDLL(_LIB_PATH)
         P = ct.POINTER
         d, i32 = ct.c_double, ct.c_int32

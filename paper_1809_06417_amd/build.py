@@ -1,5 +1,11 @@
 """Compile librte.so (HIP for gfx950) in-tree.
 
+`python -m paper_1809_06417_amd.build --sanitize` builds librte.asan.so, whose
+host code (argument validation, plan set-up, LUT builder, launch wrappers) is
+compiled with AddressSanitizer and UndefinedBehaviorSanitizer; device code is
+built as usual. The binding loads it when RTE_SANITIZE=1 is set (CPU test
+runs with clang's shared ASan runtime preloaded; see oracle/build.py).
+
 Every source is compiled with hipcc for gfx950 only. Packed-FP32 instruction
 selection is disabled (the packed forms are avoided on this target), and
 floating-point contraction is off: the kernels write their fused
@@ -18,6 +24,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librte.so")
+SAN_LIB = os.path.join(PKG, "librte.asan.so")
 SOURCES = ["rte_kernels.hip", "rte_api.cpp", "rte_lut.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,20 +44,28 @@ def _run(cmd, verbose):
     return res
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+# host-side sanitizers only (each flag applies to the host compilation)
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out_dir = os.path.join(BUILD, "asan") if sanitize else BUILD
+    os.makedirs(out_dir, exist_ok=True)
+    extra = ["-g"] + HOST_SAN if sanitize else []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(out_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        _run([HIPCC] + COMMON + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"],
+    lib = SAN_LIB if sanitize else LIB
+    tmp = lib + ".tmp"
+    link_san = HOST_SAN[:4] + ["-Xarch_host", "-shared-libsan"] if sanitize else []
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"] + link_san,
          verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)

@@ -19,7 +19,9 @@ __all__ = [
     "STATIC_SCRATCH_BYTES", "STATIC_MAX_VIEWS",
 ]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
+# RTE_SANITIZE=1: the build with sanitized host code (python -m paper_1809_06417_amd.build --sanitize)
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "librte.asan.so" if os.environ.get("RTE_SANITIZE") == "1" else "librte.so")
 
 RTE_OK, RTE_ERR_INVALID_ARG, RTE_ERR_BUDGET, RTE_ERR_HIP, RTE_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 KERNELS = {"rays": 0, "render": 1, "inscatter": 2, "gather": 3, "update": 4, "temp_map": 5,
