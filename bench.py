@@ -61,7 +61,7 @@ WORKLOADS = {
     # 4, 16 and 28 cameras, 30 iterations each
     "sweep": dict(n=128, views=0, W=256, H=256, C=1, albedo=0.0, M=0, dirs=32, iters=30, counts=(4, 16, 28)),
     "serve": dict(n=0, views=0, W=0, H=0, C=3, albedo=0.0, M=0, dirs=32, iters=10,
-                  videos=6, rate=40.0),
+                  videos=6, rate=40.0, sustainable_rate=12.0),
 }
 
 
@@ -126,9 +126,12 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or measured on a different kernel source."""
+def load_counters(kernel: str, workload: str):
+    """Counter record of `kernel` on `workload` from the committed rocprofv3
+    summary (profiles/<kernel>_<workload>_hbm_traffic.md): DRAM bytes per
+    launch (calibrated FETCH_SIZE + WRITE_SIZE) and, where measured, the
+    texture data path busy fraction. None when absent or measured on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -138,7 +141,43 @@ def load_traffic(kernel: str, workload: str):
     rec = json.loads(m.group(1))
     if rec.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return float(rec["hbm_bytes_per_launch"])
+    return rec
+
+
+def compulsory_floor(n_nodes: int, C: int, views: int, W: int, H: int) -> int:
+    """Bytes an iteration must move at least: the packed volume (emission +
+    extinction) read once per view, the frames read once and the volume update
+    written once."""
+    elem = 16 if C == 3 else 8
+    return views * n_nodes * elem + views * C * H * W * 4 + C * n_nodes * 4
+
+
+def roofline_record(dom: str, avg_s: float, alg_bytes: int, n_units: int, workload: str, launches: int,
+                    all_kernels: dict, achievable=None, floor=None):
+    """Roofline of the dominant kernel: DRAM bytes per launch (from the
+    committed counter summary) over its live average launch duration, against
+    the HBM peak. The method's logical bytes per launch (trilinear gathers and
+    per-corner accumulations, served mostly from registers, LDS and caches)
+    are reported beside it under `algorithmic`, never as `frac`."""
+    rec = load_counters(dom, workload)
+    traffic = float(rec["hbm_bytes_per_launch"]) if rec else None
+    dram = traffic / avg_s / 1e9 if traffic else None
+    out = {"bound": "hbm", "achieved": round(dram, 1) if dram else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(dram / HBM_PEAK_GBS, 4) if dram else None, "traffic": traffic, "kernel": dom,
+           "avg_ms": round(avg_s * 1e3, 4), "launches": launches,
+           "algorithmic": {"bytes_per_sample": alg_bytes // max(n_units, 1), "samples_per_launch": n_units,
+                           "GBs": round(alg_bytes / avg_s / 1e9, 1)}}
+    if rec and rec.get("td_busy") is not None:
+        out["onchip"] = {"bound": "texture data path", "busy": rec["td_busy"], "peak": 1.0,
+                         "unit": "busy cycles per cycle (rocprofv3 TD_TD_BUSY)"}
+    if floor:
+        out["floor_bytes_per_iteration"] = floor
+        if traffic:
+            out["traffic_over_floor"] = round(traffic / floor, 3)
+    if achievable:
+        out["achievable_copy_GBs"] = round(achievable, 1)
+    out["all"] = all_kernels
+    return out
 
 
 def cpu_baseline(g, rig, em, sig, frames, wl, views):
@@ -332,17 +371,19 @@ def main():
             per_kernel[k] = {"avg_ms": ms / n, "launches": n, "total_ms": ms}
     dom = max(cands, key=lambda k: ktimes[k][0])
     dom_avg_s = ktimes[dom][0] / max(ktimes[dom][1], 1) / 1e3
-    achieved = cands[dom] / dom_avg_s / 1e9
-    traffic = load_traffic(dom, args.workload)
     n_units = scat_samples if dom == "inscatter" else samples
     achievable = copy_bandwidth()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_sample": cands[dom] // n_units, "samples_per_launch": n_units,
-                "avg_ms": round(dom_avg_s * 1e3, 4), "achievable_copy_GBs": round(achievable, 1),
-                "all": {k: {"avg_ms": round(ktimes[k][0] / max(ktimes[k][1], 1), 4),
-                            "achieved_GBs": round(v / (ktimes[k][0] / max(ktimes[k][1], 1) / 1e3) / 1e9, 1)}
-                        for k, v in cands.items() if ktimes[k][1]}}
+    all_k = {}
+    for k, v in cands.items():
+        if not ktimes[k][1]:
+            continue
+        avg = ktimes[k][0] / ktimes[k][1] / 1e3
+        rec = load_counters(k, args.workload)
+        all_k[k] = {"avg_ms": round(avg * 1e3, 4), "algorithmic_GBs": round(v / avg / 1e9, 1),
+                    "dram_GBs": round(float(rec["hbm_bytes_per_launch"]) / avg / 1e9, 1) if rec else None}
+    floor = compulsory_floor(g.nx * g.ny * g.nz, C, wl["views"], wl["W"], wl["H"])
+    roofline = roofline_record(dom, dom_avg_s, cands[dom], n_units, args.workload, ktimes[dom][1], all_k,
+                               achievable, floor)
 
     base = None
     if not args.no_cpu_baseline:
@@ -418,9 +459,9 @@ def run_lovo(args, wl):
                        "pixel_rmse_test_rgb": [round(float(v), 3) for v in r["test"]],
                        "volume_rmse_rgb": [round(float(v), 3) for v in r["volume"]],
                        "scale": "0-255 (frames' maximum = 255)"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "render",
-                     "bytes_per_sample": b_render, "samples_per_launch": samples},
+        "roofline": roofline_record("render", ms / n / 1e3, b_render * samples, samples, "lovo", n,
+                                    {"render": {"avg_ms": round(ms / n, 4),
+                                                "algorithmic_GBs": round(achieved, 1)}}),
         "cpu_baseline": None,
         "kernels": {k: {"avg_ms": ms_ / n_, "launches": n_} for k, (ms_, n_) in r["kernels"].items() if n_},
     }
@@ -461,7 +502,8 @@ def run_sweep(args, wl):
 
 def run_serve(args, wl):
     """Serving: jobs arrive at Poisson times; the continuous-batching loop runs
-    them, then the same jobs run one at a time for comparison."""
+    them, then the same jobs run one at a time for comparison. Both are run at
+    the offered rate and at a sustainable rate below either path's capacity."""
     import numpy as np
     import torch
 
@@ -469,7 +511,6 @@ def run_serve(args, wl):
     from paper_1809_06417_amd import rte, serve
 
     n_jobs = args.steps
-    arrivals = synth.poisson_arrivals(n_jobs, wl["rate"], seed=args.seed)
     vids = np.random.default_rng([args.seed, 1]).integers(0, wl["videos"], size=n_jobs)
     specs = {v: synth.video_spec(v, seed=args.seed) for v in range(wl["videos"])}
     print(f"[bench] serve: {n_jobs} jobs, {wl['videos']} videos, generating frames", file=sys.stderr, flush=True)
@@ -491,7 +532,7 @@ def run_serve(args, wl):
     input_bytes = sum(F.numel() * 4 + s_.numel() * 4 for F, s_ in inputs.values())
     print(f"[bench] inputs: {input_bytes / 2**30:.1f} GiB resident", file=sys.stderr, flush=True)
 
-    def make_jobs():
+    def make_jobs(arrivals):
         return [serve.Job(i, int(v), frame_of[i], float(t), *inputs[(int(v), frame_of[i])])
                 for i, (t, v) in enumerate(zip(arrivals, vids))]
 
@@ -500,52 +541,68 @@ def run_serve(args, wl):
     # warmup: one job per video through the batched path (loads the kernels)
     warm = [serve.Job(i, v, 0, 0.0, *inputs[(v, 0)]) for i, v in enumerate(sorted(set(int(x) for x in vids)))]
     serve.serve(videos, warm, iters=min(args.warmup, wl["iters"]) or 1, hbm_budget_bytes=budget)
-    for vs in videos.values():
-        vs.volume = None
-        vs.resident = False
-        vs.busy = False
-    torch.cuda.synchronize()
-    for vs in videos.values():
-        if vs.plan is not None:
-            vs.plan.set_timing(True)
-    print("[bench] serving", file=sys.stderr, flush=True)
-    jobs = serve.serve(videos, make_jobs(), iters=wl["iters"], hbm_budget_bytes=budget,
-                       log=lambda m: None)
-    torch.cuda.synchronize()
-    summ = serve.latency_summary(jobs)
-    ktimes = {k: [0.0, 0] for k in rte.KERNELS}
-    for vs in videos.values():
-        if vs.plan is not None:
-            for k in rte.KERNELS:
-                ms, n = vs.plan.kernel_time(k)
-                ktimes[k][0] += ms
-                ktimes[k][1] += n
-            vs.plan.set_timing(False)
-    plans_resident = sum(vs.plan is not None for vs in videos.values())
-    for vs in videos.values():
-        vs.evict()
-    print(f"[bench] batched: {summ}", file=sys.stderr, flush=True)
 
-    print("[bench] one job at a time", file=sys.stderr, flush=True)
-    seq_videos = {v: serve.VideoState(s, channels=wl["C"]) for v, s in specs.items()}
-    seq = serve.serve_sequential(seq_videos, make_jobs(), iters=wl["iters"])
-    seq_summ = serve.latency_summary(seq)
-    for vs in seq_videos.values():
-        vs.evict()
-    print(f"[bench] sequential: {seq_summ}", file=sys.stderr, flush=True)
+    def reset(vs_map):
+        for vs in vs_map.values():
+            vs.volume = None
+            vs.resident = False
+            vs.busy = False
+        torch.cuda.synchronize()
 
     total_samples = sum(samples_of[int(v)] for v in vids) * wl["iters"]
-    offered = float(np.mean([samples_of[int(v)] for v in vids])) * wl["iters"] * wl["rate"]
-    value = total_samples / summ["span_s"]
+    mean_job = float(np.mean([samples_of[int(v)] for v in vids])) * wl["iters"]
+    runs = {}
+    ktimes = {k: [0.0, 0] for k in rte.KERNELS}
+    seq_videos = {v: serve.VideoState(s, channels=wl["C"]) for v, s in specs.items()}
+    for label, rate in (("offered", wl["rate"]), ("sustainable", wl["sustainable_rate"])):
+        arrivals = synth.poisson_arrivals(n_jobs, rate, seed=args.seed)
+        reset(videos)
+        timed = label == "offered"
+        if timed:
+            for vs in videos.values():
+                if vs.plan is not None:
+                    vs.plan.set_timing(True)
+        print(f"[bench] serving at {rate:g} jobs/s", file=sys.stderr, flush=True)
+        st = {}
+        jobs = serve.serve(videos, make_jobs(arrivals), iters=wl["iters"], hbm_budget_bytes=budget,
+                           log=lambda m: None, stats=st)
+        torch.cuda.synchronize()
+        summ = serve.latency_summary(jobs)
+        summ["gpu_busy"] = round(st["gpu_busy"], 4)
+        summ["samples_per_s"] = total_samples / summ["span_s"]
+        summ["served_over_offered"] = round(summ["samples_per_s"] / (mean_job * rate), 4)
+        if timed:
+            for vs in videos.values():
+                if vs.plan is not None:
+                    for k in rte.KERNELS:
+                        ms, n = vs.plan.kernel_time(k)
+                        ktimes[k][0] += ms
+                        ktimes[k][1] += n
+                    vs.plan.set_timing(False)
+        print(f"[bench] batched at {rate:g}/s: {summ}", file=sys.stderr, flush=True)
+        reset(seq_videos)
+        print(f"[bench] one job at a time at {rate:g} jobs/s", file=sys.stderr, flush=True)
+        seq = serve.serve_sequential(seq_videos, make_jobs(arrivals), iters=wl["iters"])
+        seq_summ = serve.latency_summary(seq)
+        seq_summ["samples_per_s"] = total_samples / seq_summ["span_s"]
+        seq_summ["served_over_offered"] = round(seq_summ["samples_per_s"] / (mean_job * rate), 4)
+        print(f"[bench] sequential at {rate:g}/s: {seq_summ}", file=sys.stderr, flush=True)
+        runs[label] = {"rate_jobs_per_s": rate, "offered_samples_per_s": mean_job * rate,
+                       "batched": summ, "one_at_a_time": seq_summ}
+    plans_resident = sum(vs.plan is not None for vs in videos.values())
+    for vs in list(videos.values()) + list(seq_videos.values()):
+        vs.evict()
+
+    summ = runs["offered"]["batched"]
+    value = summ["samples_per_s"]
     b_render, b_gather = bytes_per_sample(wl["C"], False)
     cands = {"render": b_render, "gather": b_gather}
     dom = max(cands, key=lambda k: ktimes[k][0])
     # aggregated over every batched launch: algorithmic bytes / kernel time
-    achieved = cands[dom] * total_samples / (ktimes[dom][0] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom + " (batched)",
-                "bytes_per_sample": cands[dom], "launches": ktimes[dom][1],
-                "avg_ms": ktimes[dom][0] / max(ktimes[dom][1], 1)}
+    avg_s = ktimes[dom][0] / max(ktimes[dom][1], 1) / 1e3
+    roofline = roofline_record(dom, avg_s, cands[dom] * total_samples // max(ktimes[dom][1], 1),
+                               total_samples // max(ktimes[dom][1], 1), "serve", ktimes[dom][1], {})
+    roofline["kernel"] = dom + " (batched)"
     per_kernel = {k: {"avg_ms": ms / n, "launches": n, "total_ms": ms} for k, (ms, n) in ktimes.items() if n}
     out = {
         "metric": "ray samples/s per render+backproject iteration",
@@ -562,13 +619,15 @@ def run_serve(args, wl):
         "data": "synthetic",
         "config": {"workload": f"serve: {n_jobs} frame jobs from {wl['videos']} seeded videos "
                                f"(grids 64-256^3, 4-12 views, 256^2-1024x768, RGB, no scattering), "
-                               f"Poisson arrivals at {wl['rate']:g} jobs/s, {wl['iters']} SART iterations "
-                               f"per job warm-started from the resident previous volume",
+                               f"Poisson arrivals at {wl['rate']:g} jobs/s (and at {wl['sustainable_rate']:g} "
+                               f"jobs/s), {wl['iters']} SART iterations per job warm-started from the "
+                               f"resident previous volume; batched loop on 2 stream lanes, 2 steps queued each",
                    "videos": {v: f"{s.grid.nx}^3, {s.rig.n_views} views of {s.rig.width}x{s.rig.height}, "
                                  f"{samples_of[v]} samples/iteration" for v, s in specs.items()},
                    "hbm_budget_gib": args.hbm_budget_gib, "plans_resident": plans_resident,
-                   "offered_samples_per_s": offered, "utilisation": value / offered},
-        "serving": {"batched": summ, "one_at_a_time": seq_summ},
+                   "offered_samples_per_s": mean_job * wl["rate"],
+                   "utilisation": summ["served_over_offered"]},
+        "serving": runs,
         "roofline": roofline,
         "cpu_baseline": None,
         "kernels": per_kernel,
