@@ -3,15 +3,25 @@
 Jobs (one video frame each: frames, the frame's extinction, a fixed number of
 SART iterations, warm-started from the video's previous result) arrive over
 time. The loop admits waiting jobs whenever their video is idle, a batch slot
-is free and the video's plan fits in the HBM budget (idle plans are evicted,
-least recently used first; every video's latest volume stays resident on the
-device). All admitted jobs then advance together, one iteration per step,
-each step being one batched launch per phase (rte_job_step); a job leaves the
-batch when its iterations are done and the next one can join at the very next
-step. Per-job results are bitwise the ones each job gets alone.
+is free and the device memory the job needs fits the HBM budget: the video's
+plan workspace, its resident volume and the job's frames and extinction
+(idle plans are evicted, least recently used first; every video's latest
+volume stays resident on the device to warm-start its next frame).
+
+Admitted jobs are spread over `lanes` HIP streams (the lane with the fewest
+march samples per iteration takes the next job, for the job's whole life).
+Each lane advances all of its jobs together, one iteration per batched
+launch per phase (rte_job_step), and keeps up to `depth` steps queued ahead
+of the GPU, so one lane's render runs beside another lane's back-projection
+and the GPU never waits for the host between steps. A job leaves its lane
+when its iterations are enqueued; a completion event recorded after its last
+kernels tells the host when it is done (no device-wide synchronisation), and
+the next job of the same video is admitted only then. Every job runs the same
+kernels in the same order on one stream, so its result is bitwise the one it
+gets alone.
 
 The one-job-at-a-time reference (`serve_sequential`) runs the same jobs in
-arrival order with rte_reconstruct.
+arrival order with rte_reconstruct on one stream.
 """
 from __future__ import annotations
 
@@ -23,7 +33,7 @@ import numpy as np
 
 from . import rte
 
-__all__ = ["Job", "VideoState", "serve", "serve_sequential", "latency_summary"]
+__all__ = ["Job", "VideoState", "serve", "serve_sequential", "latency_summary", "min_budget"]
 
 
 @dataclasses.dataclass
@@ -38,6 +48,10 @@ class Job:
     done: float | None = None
     iters: int = 0
     result: object = None               # copy of the result (keep_results)
+    lane: int = -1
+
+    def input_bytes(self):
+        return 4 * (self.frames.numel() + self.extinction.numel())
 
 
 class VideoState:
@@ -46,6 +60,9 @@ class VideoState:
         self.channels = channels
         self.plan = None
         self.plan_bytes = rte.workspace_bytes(spec.grid, spec.rig, channels=channels)
+        g = spec.grid
+        self.volume_bytes = 4 * channels * g.nx * g.ny * g.nz
+        self.samples = None      # march samples per iteration (known once a plan exists)
         self.volume = None       # latest result, resident on the device
         self.resident = False    # the plan's packed volume holds self.volume
         self.busy = False
@@ -54,6 +71,7 @@ class VideoState:
     def ensure_plan(self):
         if self.plan is None:
             self.plan = rte.Plan(self.spec.grid, self.spec.rig, channels=self.channels)
+            self.samples = self.plan.samples
             self.resident = False
         return self.plan
 
@@ -72,6 +90,13 @@ def latency_summary(jobs):
             "frames_per_s": len(jobs) / span, "span_s": span}
 
 
+def min_budget(videos, jobs):
+    """Smallest HBM budget that admits every job: the largest plan, every
+    video's resident volume and the largest job's inputs."""
+    return (max(v.plan_bytes for v in videos.values()) + sum(v.volume_bytes for v in videos.values())
+            + max(j.input_bytes() for j in jobs))
+
+
 def _zeros_volume(vs):
     import torch
     g = vs.spec.grid
@@ -79,78 +104,122 @@ def _zeros_volume(vs):
 
 
 def serve(videos, jobs, iters=10, hbm_budget_bytes=32 << 30, max_batch=64, keep_results=False,
-          clock=time.perf_counter, log=None):
+          clock=time.perf_counter, log=None, lanes=2, depth=2, stats=None):
     """Run `jobs` (sorted by arrival) through the continuous-batching loop.
-    videos: {video id: VideoState}. Returns the jobs with start/done times."""
+    videos: {video id: VideoState}. Returns the jobs with start/done times.
+    stats (a dict, optional) receives the GPU-busy fraction of the span (time
+    with at least one step or job end not yet complete) and the step count."""
     import torch
-    for j in jobs:
-        if videos[j.video].plan_bytes > hbm_budget_bytes:
-            raise ValueError(f"video {j.video} needs {videos[j.video].plan_bytes} B of workspace, "
-                             f"more than the budget of {hbm_budget_bytes} B")
+    need = min_budget(videos, jobs) if jobs else 0
+    if need > hbm_budget_bytes:
+        raise ValueError(f"the jobs need at least {need} B (largest plan, resident volumes, largest job "
+                         f"inputs), more than the budget of {hbm_budget_bytes} B")
+    streams = [torch.cuda.Stream() for _ in range(lanes)]  # default priority
     pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
-    waiting, active = [], []
-    used = sum(v.plan.device_bytes for v in videos.values() if v.plan is not None)
+    waiting = []
+    lane_jobs = [[] for _ in range(lanes)]
+    inflight = [collections.deque() for _ in range(lanes)]   # events after each queued step
+    finishing = []                                           # (job, event after its job end)
+
+    def used_bytes():
+        n = sum(v.plan.device_bytes for v in videos.values() if v.plan is not None)
+        n += sum(v.volume_bytes for v in videos.values() if v.volume is not None)
+        n += sum(j.input_bytes() for lj in lane_jobs for j in lj)
+        n += sum(j.input_bytes() for j, _ in finishing)
+        return n
+
     t0 = clock()
     steps = 0
-    while pending or waiting or active:
+    busy_s = 0.0
+    t_prev = 0.0
+    while pending or waiting or finishing or any(lane_jobs):
         now = clock() - t0
+        if any(inflight) or finishing:
+            busy_s += now - t_prev
+        t_prev = now
         while pending and pending[0].arrival <= now:
             waiting.append(pending.popleft())
+        # completions
+        for l in range(lanes):
+            while inflight[l] and inflight[l][0].query():
+                inflight[l].popleft()
+        for item in list(finishing):
+            job, ev = item
+            if ev.query():
+                t = clock() - t0
+                job.done = t
+                vs = videos[job.video]
+                vs.busy = False
+                vs.last_used = t
+                finishing.remove(item)
+                if log:
+                    log(f"t={t:7.3f}s done job {job.jid} (waiting {len(waiting)})")
         # admission: FIFO among jobs whose video is idle
+        n_active = sum(len(lj) for lj in lane_jobs)
         for job in list(waiting):
-            if len(active) >= max_batch:
+            if n_active >= max_batch:
                 break
             vs = videos[job.video]
             if vs.busy:
                 continue
+            extra = job.input_bytes() + (vs.volume_bytes if vs.volume is None else 0)
             if vs.plan is None:
-                while used + vs.plan_bytes > hbm_budget_bytes:
+                extra += vs.plan_bytes
+                while used_bytes() + extra > hbm_budget_bytes:
                     idle = [v for v in videos.values() if v.plan is not None and not v.busy and v is not vs]
                     if not idle:
                         break
-                    lru = min(idle, key=lambda v: v.last_used)
-                    used -= lru.plan.device_bytes
-                    lru.evict()
-                if used + vs.plan_bytes > hbm_budget_bytes:
-                    continue
-                vs.ensure_plan()
-                used += vs.plan.device_bytes
-            warm = None if vs.resident else (vs.volume if vs.volume is not None else _zeros_volume(vs))
-            vs.plan.job_begin(job.frames, job.extinction, warm)
+                    min(idle, key=lambda v: v.last_used).evict()
+            if used_bytes() + extra > hbm_budget_bytes:
+                continue
+            vs.ensure_plan()
+            lane = min(range(lanes), key=lambda l: sum(videos[j.video].samples for j in lane_jobs[l]))
+            with torch.cuda.stream(streams[lane]):
+                if vs.volume is None:
+                    vs.volume = _zeros_volume(vs)
+                warm = None if vs.resident else vs.volume
+                vs.plan.job_begin(job.frames, job.extinction, warm)
             vs.busy = True
             job.start = clock() - t0
             job.iters = 0
-            active.append(job)
+            job.lane = lane
+            lane_jobs[lane].append(job)
             waiting.remove(job)
-        if not active:
-            if pending:
-                time.sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.05)))
-            continue
-        rte.job_step([videos[j.video].plan for j in active])
-        steps += 1
-        finished = []
-        for j in active:
-            j.iters += 1
-            if j.iters == iters:
-                vs = videos[j.video]
-                if vs.volume is None:
-                    vs.volume = _zeros_volume(vs)
-                vs.plan.job_end(vs.volume)
-                vs.resident = True
-                if keep_results:
-                    j.result = vs.volume.clone()
-                finished.append(j)
-        torch.cuda.synchronize()
-        if finished:
-            t = clock() - t0
-            for j in finished:
-                j.done = t
-                vs = videos[j.video]
-                vs.busy = False
-                vs.last_used = t
-                active.remove(j)
-            if log:
-                log(f"t={t:7.3f}s done {len(finished)} (active {len(active)}, waiting {len(waiting)})")
+            n_active += 1
+        # issue: each lane keeps up to `depth` steps queued
+        issued = False
+        for l in range(lanes):
+            if not lane_jobs[l] or len(inflight[l]) >= depth:
+                continue
+            with torch.cuda.stream(streams[l]):
+                rte.job_step([videos[j.video].plan for j in lane_jobs[l]])
+                steps += 1
+                for j in list(lane_jobs[l]):
+                    j.iters += 1
+                    if j.iters == iters:
+                        vs = videos[j.video]
+                        vs.plan.job_end(vs.volume)
+                        vs.resident = True
+                        if keep_results:
+                            j.result = vs.volume.clone()
+                        ev = torch.cuda.Event()
+                        ev.record(streams[l])
+                        finishing.append((j, ev))
+                        lane_jobs[l].remove(j)
+                ev = torch.cuda.Event()
+                ev.record(streams[l])
+                inflight[l].append(ev)
+            issued = True
+        if not issued:
+            # nothing to enqueue: wait a little for a completion or an arrival
+            time.sleep(0.0002 if (any(inflight) or finishing) else
+                       max(0.0, min(pending[0].arrival - (clock() - t0), 0.05)) if pending else 0.0002)
+    for st in streams:
+        st.synchronize()
+    if stats is not None:
+        span = max(j.done for j in jobs) - min(j.arrival for j in jobs) if jobs else 0.0
+        stats.update({"gpu_busy": busy_s / span if span > 0 else 0.0, "steps": steps, "lanes": lanes,
+                      "depth": depth})
     return jobs
 
 

@@ -193,16 +193,17 @@ def test_job_api_rejects_bad_batches():
         b.close()
 
 
-@pytest.mark.parametrize("budget", ["ample", "one_plan"])
-def test_serving_loop_matches_sequential(budget):
-    """The continuous-batching loop (with LRU eviction of idle plans when the
-    HBM budget holds only one plan) returns, per job, bitwise the volume of
-    the one-job-at-a-time reference in arrival order."""
+@pytest.mark.parametrize("budget, lanes", [("ample", 2), ("one_plan", 2), ("ample", 1), ("ample", 3)])
+def test_serving_loop_matches_sequential(budget, lanes):
+    """The continuous-batching loop (on 1-3 stream lanes with steps queued
+    ahead, and with LRU eviction of idle plans when the HBM budget holds only
+    one plan besides the resident volumes) returns, per job, bitwise the
+    volume of the one-job-at-a-time reference in arrival order."""
     import torch
     from paper_1809_06417_amd import serve
     arrivals = synth.poisson_arrivals(12, 400.0, seed=2)
     vids = np.random.default_rng(4).integers(0, len(SMALL), size=len(arrivals))
-    say("serving loop", budget)
+    say("serving loop", budget, lanes)
 
     def make_jobs():
         count = {}
@@ -222,8 +223,11 @@ def test_serving_loop_matches_sequential(budget):
         inputs[(int(v), fr)] = frame_inputs(SMALL[int(v)], fr)
 
     videos = {i: serve.VideoState(s) for i, s in enumerate(SMALL)}
-    cap = max(v.plan_bytes for v in videos.values()) + 1 if budget == "one_plan" else 1 << 34
-    jobs = serve.serve(videos, make_jobs(), iters=4, hbm_budget_bytes=cap, keep_results=True)
+    cap = serve.min_budget(videos, make_jobs()) if budget == "one_plan" else 1 << 34
+    st = {}
+    jobs = serve.serve(videos, make_jobs(), iters=4, hbm_budget_bytes=cap, keep_results=True, lanes=lanes,
+                       stats=st)
+    assert 0.0 < st["gpu_busy"] <= 1.01
     for v in videos.values():
         v.evict()
     ref_videos = {i: serve.VideoState(s) for i, s in enumerate(SMALL)}
