@@ -31,6 +31,8 @@ Parity status of each function (what pins it, see ``tests/test_oracle_pins.py``)
                        stop rule)
   planck / band / lut  pinned (Stefan-Boltzmann integral, Wien peak, LUT vs
                        direct integral within the interpolation bound)
-  temperature_fit      pinned (fixed point at the true temperature, residual descent)
+  temperature_fit      pinned (fixed point at the true temperature, residual descent, one and
+                       two iterations from another start against the EM step on a dense
+                       matrix rebuilt at each iteration's temperature)
 """
 from .oracle import *  # noqa: F401,F403
