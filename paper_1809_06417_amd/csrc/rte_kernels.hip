@@ -47,21 +47,19 @@ static inline int grid8(int64_t blocks) { return (int)(((blocks + 7) / 8) * 8); 
 // from the entry and length len; the last segment is clipped at the exit.
 __device__ __forceinline__ void segment_of(int k, int K, float L, float ds, float &s, float &len)
 {
-    if (k < K - 1) {
-        s = ((float)k + 0.5f) * ds;
-        len = ds;
-    } else {
-        const float a = (float)k * ds;
-        len = fminf(fmaxf(L - a, 0.0f), ds);
-        s = fmaf(0.5f, len, a);
-    }
+    // both forms are evaluated and one is selected (no branch in the march loops)
+    const float a = (float)k * ds;
+    const float len_last = __builtin_amdgcn_fmed3f(L - a, 0.0f, ds);
+    const bool inner = k < K - 1;
+    len = inner ? ds : len_last;
+    s = inner ? ((float)k + 0.5f) * ds : fmaf(0.5f, len_last, a);
 }
 
 // Clamp a grid coordinate to [0, n-1] and split it into a cell index
 // (<= n-2) and the fraction inside the cell.
 __device__ __forceinline__ void cell_of(float x, int n, int &i, float &f)
 {
-    x = fminf(fmaxf(x, 0.0f), (float)(n - 1));
+    x = __builtin_amdgcn_fmed3f(x, 0.0f, (float)(n - 1));
     i = min((int)x, n - 2);
     f = x - (float)i;
 }
@@ -1319,7 +1317,11 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
         }
         // one candidate pixel ray: slab test against the padded cell, then
         // every sample of the ray that the render placed in this cell
-        auto candidate = [&](int px, int py, int r, const float4 &A, const float4 &B) {
+        constexpr bool kReadsG = MODE == kGatherAdjoint || MODE == kGatherAdjointCols || MODE == kGatherGrad;
+        auto tile_of = [&](int px, int py) { return v * a.tiles_per_view + (py >> 3) * a.tiles_x + (px >> 3); };
+        // toff: first slot of the candidate's tile in the per-sample buffers
+        // (loaded with the candidate's ray, one candidate ahead)
+        auto candidate = [&](int px, int py, int r, const float4 &A, const float4 &B, uint32_t toff) {
             if ((MODE == kGatherHull || MODE == kGatherAdjointCols) && a.rowmask &&
                 a.rowmask[r] == 0.0f)
                 return;
@@ -1357,8 +1359,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                     yv[0] = a.y[r];
                 }
             }
-            const int tile = v * a.tiles_per_view + (py >> 3) * a.tiles_x + (px >> 3);
-            const float *gp = a.g + a.tile_off[tile] + ((py & 7) * 8 + (px & 7));
+            const float *gp = a.g + toff + ((py & 7) * 8 + (px & 7));
             for (int k = k_lo; k <= k_hi; ++k) {
                 float s, len;
                 segment_of(k, K, A.w, a.ds, s, len);
@@ -1430,10 +1431,12 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
             const int ncand = (u1 >= u0 && v1 >= v0) ? (u1 - u0 + 1) * (v1 - v0 + 1) : 0;
             int nxp = u0, nyp = v0;
             float4 An = make_float4(0.f, 0.f, 0.f, 0.f), Bn = An;
+            uint32_t Tn = 0;
             if (ncand > 0) {
                 const int rn = v * HW + nyp * a.W + nxp;
                 An = a.rayA[rn];
                 Bn = a.rayB[rn];
+                if constexpr (kReadsG) Tn = a.tile_off[tile_of(nxp, nyp)];
             }
             for (int i = 0; i < ncand && !found; ++i) {
                 const int px = nxp, py = nyp;
@@ -1442,18 +1445,20 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                     ++nyp;
                 }
                 const float4 A = An, B = Bn;
+                const uint32_t T = Tn;
                 if (i + 1 < ncand) {
                     const int rn = v * HW + nyp * a.W + nxp;
                     An = a.rayA[rn];
                     Bn = a.rayB[rn];
+                    if constexpr (kReadsG) Tn = a.tile_off[tile_of(nxp, nyp)];
                 }
-                candidate(px, py, v * HW + py * a.W + px, A, B);
+                candidate(px, py, v * HW + py * a.W + px, A, B, T);
             }
         } else {
             for (int py = v0; py <= v1; ++py) {
                 for (int px = u0; px <= u1; ++px) {
                     const int r = v * HW + py * a.W + px;
-                    candidate(px, py, r, a.rayA[r], a.rayB[r]);
+                    candidate(px, py, r, a.rayA[r], a.rayB[r], 0u);
                 }
             }
         }
