@@ -336,7 +336,9 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
  * (RTE_ERR_UNSUPPORTED otherwise).
  * rte_job_step advances every listed plan (1..64 distinct plans with open
  * jobs, one channel count, update rule and scattering setting) by one
- * iteration with one launch per phase covering all of them, except that the
+ * iteration with one launch per phase covering all of them (with
+ * in-scattering, one launch per march pass and reduce computes every plan's
+ * grid; its arguments are staged in the first listed plan), except that the
  * first step of a SART or EM job runs on its own (its render also stores the
  * per-sample weights and its gather the column sums, as the first iteration
  * of rte_reconstruct does); each plan's result is bitwise the one it would
@@ -345,7 +347,8 @@ int rte_reconstruct(rte_plan *plan, const float *frames, const float *extinction
  * plan past its first step, or any paper-rule plan): issue all steps that
  * share it on one stream. With timing on, the three batched launches are
  * charged to that plan (RTE_KERNEL_RENDER, _GATHER, _UPDATE), a first step's
- * launches to its own plan.
+ * launches to its own plan, the batched in-scatter to the first listed plan
+ * (RTE_KERNEL_INSCATTER).
  * Errors: RTE_ERR_INVALID_ARG for a plan without an open job or listed twice,
  * RTE_ERR_UNSUPPORTED for more than 64 plans or mixed settings; no plan is
  * advanced then.

@@ -41,6 +41,7 @@ int ok()
 constexpr int kMaxLut = 65536;
 constexpr int kMaxBatch = 64;          // plans per rte_job_step
 constexpr size_t kBatchBytes = 1 << 17; // staging for their launch arguments
+constexpr size_t kScatStageBytes = 1 << 15;  // of which the batched in-scatter's region
 constexpr int kMaxDirs = 256;
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -306,6 +307,7 @@ void free_plan(rte_plan *p)
     if (p->h_err_sum) hipHostFree(p->h_err_sum);
     if (p->h_batch) hipHostFree(p->h_batch);
     if (p->batch_event) hipEventDestroy(p->batch_event);
+    if (p->scat_event) hipEventDestroy(p->scat_event);
     if (p->d_batch) hipFree(p->d_batch);
     delete p;
 }
@@ -492,11 +494,15 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         (rc = dev_alloc(&p->d_err_sum, 2 * sizeof(double), acc)))
         return bail(rc);
     if ((rc = dev_alloc(&p->d_batch, kBatchBytes, acc))) return bail(rc);
-    p->batch_bytes = kBatchBytes;
+    p->batch_bytes = kBatchBytes - kScatStageBytes;
+    p->scat_stage_off = kBatchBytes - kScatStageBytes;
+    p->scat_stage_bytes = kScatStageBytes;
     if (hipHostMalloc((void **)&p->h_err_sum, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&p->h_batch, kBatchBytes, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&p->batch_event, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(p->batch_event, s) != hipSuccess)
+        hipEventRecord(p->batch_event, s) != hipSuccess ||
+        hipEventCreateWithFlags(&p->scat_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(p->scat_event, s) != hipSuccess)
         return bail(fail(RTE_ERR_HIP, "pinned host allocation failed"));
     // in-scatter directions: spherical Fibonacci, voxel units per world unit
     if (M) {
@@ -957,8 +963,9 @@ int rte_job_step(rte_plan *const *plans, int32_t n, void *stream)
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool scat = p0->params.albedo > 0.0f && p0->params.scatter_res >= 2;
-    if (scat)
-        for (int i = 0; i < n; ++i) RTE_LAUNCH(plans[i], RTE_KERNEL_INSCATTER, s, rte::launch_inscatter(plans[i], nullptr, s));
+    // every plan's in-scatter grid, one launch per pass for all of them
+    // (timing charged to the first listed plan)
+    if (scat) RTE_LAUNCH(plans[0], RTE_KERNEL_INSCATTER, s, rte::launch_inscatter_batch(plans, n, s));
     // the first step of a SART or EM job runs alone, as the first iteration
     // of rte_reconstruct does: its render also stores the per-sample weights
     // and its gather also accumulates the column sums that the later steps

@@ -115,7 +115,9 @@ struct rte_plan {
     void *d_batch = nullptr;        // device copy of batched launch arguments
     void *h_batch = nullptr;        // pinned host staging of the same
     hipEvent_t batch_event = nullptr;  // marks the end of the last upload from h_batch
-    size_t batch_bytes = 0;
+    size_t batch_bytes = 0;            // [0, batch_bytes): render, gather and update arguments
+    size_t scat_stage_off = 0, scat_stage_bytes = 0;  // region of batched in-scatter arguments
+    hipEvent_t scat_event = nullptr;   // marks the end of the last upload from that region
     std::vector<float> last_errors; // image RMS per iteration of the last reconstruction (stop rule)
     int lut_cap = 0;
     int part_acc = 0;               // accumulators per corner the partial buffer holds
@@ -158,6 +160,9 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
 hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const double *exit_tau, const float *dI,
                                 hipStream_t s);
 hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s);
+// The in-scatter grids of n plans with one launch per march pass and reduce
+// (arguments staged through plans[0]'s in-scatter region).
+hipError_t launch_inscatter_batch(rte_plan *const *plans, int n, hipStream_t s);
 hipError_t launch_gather(const rte_plan *p, int channels, int mode, const float *y,
                          float alpha_l, float alpha_d, float tau, hipStream_t s,
                          const float *rowmask = nullptr, float g_sigma = 0.f, uint64_t seed = 0,

@@ -982,17 +982,17 @@ struct ScatArgs {
 // the sums on nothing but the loads). Each (direction, node) sum is stored;
 // the directions are added in order by inscatter_reduce_kernel.
 template <int C>
-__global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
+__device__ __forceinline__ void inscatter_march_body(const ScatArgs &a, const int pass, const int blk)
 {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int x = blk & 7, j = blk >> 3;
     const int M = a.M, bm = (M + 3) >> 2;
     int d, bx, by, bz, start = 0;
     if (a.xslab) {
         // XCD x marches slab x: in pass p, the up-going rays of the nodes that
         // start in slab x - p and the down-going rays of those starting in
         // slab x + p (a ray crosses one slab per pass)
-        const int s_up = x - a.pass, s_dn = x + a.pass;
+        const int s_up = x - pass, s_dn = x + pass;
         const int bxy = bm * bm;
         const int nl_up = s_up >= 0 ? max(a.bz_hi[s_up] - a.bz_lo[s_up] + 1, 0) : 0;
         const int nl_dn = s_dn < a.npass ? max(a.bz_hi[s_dn] - a.bz_lo[s_dn] + 1, 0) : 0;
@@ -1051,7 +1051,7 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
     float acc[C];
     float T = 1.0f;
     int k0 = 0;
-    if (a.pass == 0) {
+    if (pass == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0.0f;
     } else {
@@ -1064,9 +1064,9 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
     const bool up = u.z >= 0.0f;
     // the slab marched in this pass; the edge slab, and any slab in the final
     // pass, takes every remaining sample
-    const int slab = a.xslab ? x : (up ? a.pass : a.npass - 1 - a.pass);
-    const bool last = a.xslab ? ((up ? slab == a.npass - 1 : slab == 0) || a.pass == kScatFinalPass)
-                              : a.pass == a.npass - 1;
+    const int slab = a.xslab ? x : (up ? pass : a.npass - 1 - pass);
+    const bool last = a.xslab ? ((up ? slab == a.npass - 1 : slab == 0) || pass == kScatFinalPass)
+                              : pass == a.npass - 1;
     const float zlo = (float)slab * a.slab_h, zhi = (float)(slab + 1) * a.slab_h;
     // software pipeline: the corner loads of sample k + 1 are in flight
     // while sample k is accumulated (the positions do not depend on the sums)
@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
         fy = fy2;
         fz = fz2;
     }
-    if (k == k0 && a.pass > 0) return;  // nothing in this slab: the state stands
+    if (k == k0 && pass > 0) return;  // nothing in this slab: the state stands
     if (!last) {
         a.kstate[st] = k;
         a.tstate[st] = T;
@@ -1134,14 +1134,31 @@ __global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
     for (int c = 0; c < C; ++c) a.dpart[(int64_t)(d * C + c) * m3 + m] = acc[c];
 }
 
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_march_kernel(ScatArgs a)
+{
+    inscatter_march_body<C>(a, a.pass, blockIdx.x);
+}
+
+// One pass of several plans' in-scatter marches in one launch: prefix[j] is
+// the first block of plan j (a multiple of 8, so every block keeps the XCD it
+// has in the plan's own launch); plans without this pass have no blocks.
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_march_batch_kernel(const ScatArgs *args, const int *prefix,
+                                                                      int n, int pass)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    inscatter_march_body<C>(args[j], pass, blockIdx.x - prefix[j]);
+}
+
 // S_c(node) = (1 / ndirs) sum_d, the directions added in index order. Small
 // blocks: a 32^3 grid is 512 of them, enough to reach every CU.
 constexpr int kReduceBlock = 64;
 template <int C>
-__global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_kernel(ScatArgs a)
+__device__ __forceinline__ void inscatter_reduce_body(const ScatArgs &a, const int blk)
 {
     const int m3 = a.M * a.M * a.M;
-    const int m = blockIdx.x * kReduceBlock + threadIdx.x;
+    const int m = blk * kReduceBlock + threadIdx.x;
     if (m >= m3) return;
     float tot[C];
 #pragma unroll
@@ -1167,6 +1184,20 @@ __global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_kernel(ScatArgs
     }
 }
 
+template <int C>
+__global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_kernel(ScatArgs a)
+{
+    inscatter_reduce_body<C>(a, blockIdx.x);
+}
+
+template <int C>
+__global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_batch_kernel(const ScatArgs *args, const int *prefix,
+                                                                             int n)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    inscatter_reduce_body<C>(args[j], blockIdx.x - prefix[j]);
+}
+
 // Henyey-Greenstein in-scattering (Eq. 9, g != 0): view v sees at node p the
 // incident radiance of every direction u_d weighted by p(w, u_d), w the
 // direction from p to the camera centre (the direction the scattered light
@@ -1176,11 +1207,10 @@ __global__ __launch_bounds__(kReduceBlock) void inscatter_reduce_kernel(ScatArgs
 // 1 + g^2 + 2 g cos is a difference of nearly equal terms. One work-item per
 // (node, view); directions are added in index order.
 template <int C>
-__global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_kernel(ScatArgs a)
+__device__ __forceinline__ void inscatter_phase_reduce_body(const ScatArgs &a, const int blk, const int v)
 {
     const int m3 = a.M * a.M * a.M;
-    const int m = blockIdx.x * kBlock + threadIdx.x;
-    const int v = blockIdx.y;
+    const int m = blk * kBlock + threadIdx.x;
     if (m >= m3 || v >= a.V) return;
     const int M = a.M, mx = m % M, my = (m / M) % M, mz = m / (M * M);
     const rte_camera &cam = a.cams[v];
@@ -1221,6 +1251,25 @@ __global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_kernel(ScatArgs
 #pragma unroll
         for (int c = 0; c < C; ++c) a.planar[(int64_t)(v * C + c) * m3 + m] = out[c];
     }
+}
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_kernel(ScatArgs a)
+{
+    inscatter_phase_reduce_body<C>(a, blockIdx.x, blockIdx.y);
+}
+
+// Several plans' per-view reductions in one launch: plan j has
+// ceil(M^3 / kBlock) blocks per view, views one after another.
+template <int C>
+__global__ __launch_bounds__(kBlock) void inscatter_phase_reduce_batch_kernel(const ScatArgs *args,
+                                                                             const int *prefix, int n)
+{
+    const int j = batch_job(prefix, n, blockIdx.x);
+    const ScatArgs &a = args[j];
+    const int per_view = (a.M * a.M * a.M + kBlock - 1) / kBlock;
+    const int local = blockIdx.x - prefix[j];
+    inscatter_phase_reduce_body<C>(a, local % per_view, local / per_view);
 }
 
 // ---------------------------------------------------------------- K3 gather
@@ -1981,7 +2030,8 @@ hipError_t launch_render(const rte_plan *p, int channels, bool use_emission, boo
     return render_dispatch<1>(a, use_emission, use_scatter, write_g, epilogue, s);
 }
 
-hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
+// Arguments of a plan's in-scatter launches (every pass, and the reduce).
+static ScatArgs scat_args(const rte_plan *p, float *planar_out)
 {
     ScatArgs a{};
     a.vol = p->d_vol;
@@ -2007,7 +2057,6 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     a.nbricks = bm * bm * bm;
     a.blocks_per_dir = (a.nbricks + 3) / 4;
     a.dirs_per_xcd = (a.ndirs + 7) / 8;
-    const int nb = 8 * a.dirs_per_xcd * a.blocks_per_dir;
     const int64_t m3 = (int64_t)a.M * a.M * a.M;
     const int C = p->params.channels;
     a.kstate = reinterpret_cast<int *>(a.dpart + (int64_t)a.ndirs * C * m3);
@@ -2053,24 +2102,39 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
             a.hs[i] = (p->grid.bbox_max[i] - p->grid.bbox_min[i]) / (double)(a.M - 1);
         }
     }
+    return a;
+}
+
+static int scat_passes(const ScatArgs &a) { return a.xslab ? kScatFinalPass + 1 : a.npass; }
+
+// Blocks of march pass `pass` (0: nothing to march in it).
+static int scat_pass_blocks(const ScatArgs &a, int pass)
+{
+    if (!a.xslab) return 8 * a.dirs_per_xcd * a.blocks_per_dir;
+    // blocks per XCD: its up and down (direction, brick) items, 4 per block
+    const int bxy = ((a.M + 3) / 4) * ((a.M + 3) / 4);
+    int64_t most = 0;
+    for (int xx = 0; xx < 8; ++xx) {
+        const int su = xx - pass, sd = xx + pass;
+        const int64_t nu = su >= 0 ? std::max(a.bz_hi[su] - a.bz_lo[su] + 1, 0) : 0;
+        const int64_t ndn = sd < a.npass ? std::max(a.bz_hi[sd] - a.bz_lo[sd] + 1, 0) : 0;
+        const int64_t items = (int64_t)a.nup * nu * bxy + (int64_t)(a.ndirs - a.nup) * ndn * bxy;
+        most = std::max(most, (items + 3) / 4);
+    }
+    return (int)(8 * most);
+}
+
+hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
+{
+    ScatArgs a = scat_args(p, planar_out);
+    const int C = p->params.channels;
+    const int64_t m3 = (int64_t)a.M * a.M * a.M;
+    const bool phase = scat_view_stride(p) != 0;
     const dim3 rgrid((unsigned)blocks_for(m3), phase ? (unsigned)p->V : 1u);
     const dim3 sgrid((unsigned)((m3 + kReduceBlock - 1) / kReduceBlock));
-    for (a.pass = 0; a.pass < (a.xslab ? kScatFinalPass + 1 : a.npass); ++a.pass) {
-        int nbp = nb;
-        if (a.xslab) {
-            // blocks per XCD: its up and down (direction, brick) items, 4 per block
-            const int bxy = ((a.M + 3) / 4) * ((a.M + 3) / 4);
-            int64_t most = 0;
-            for (int xx = 0; xx < 8; ++xx) {
-                const int su = xx - a.pass, sd = xx + a.pass;
-                const int64_t nu = su >= 0 ? std::max(a.bz_hi[su] - a.bz_lo[su] + 1, 0) : 0;
-                const int64_t ndn = sd < a.npass ? std::max(a.bz_hi[sd] - a.bz_lo[sd] + 1, 0) : 0;
-                const int64_t items = (int64_t)a.nup * nu * bxy + (int64_t)(a.ndirs - a.nup) * ndn * bxy;
-                most = std::max(most, (items + 3) / 4);
-            }
-            if (most == 0) continue;
-            nbp = (int)(8 * most);
-        }
+    for (a.pass = 0; a.pass < scat_passes(a); ++a.pass) {
+        const int nbp = scat_pass_blocks(a, a.pass);
+        if (nbp == 0) continue;
         if (C == 3) hipLaunchKernelGGL(inscatter_march_kernel<3>, dim3(nbp), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL(inscatter_march_kernel<1>, dim3(nbp), dim3(kBlock), 0, s, a);
     }
@@ -2080,6 +2144,71 @@ hipError_t launch_inscatter(const rte_plan *p, float *planar_out, hipStream_t s)
     } else {
         if (phase) hipLaunchKernelGGL(inscatter_phase_reduce_kernel<1>, rgrid, dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL(inscatter_reduce_kernel<1>, sgrid, dim3(kReduceBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// The in-scatter grids of n plans (one channel count) with one launch per
+// march pass and one per kind of reduce, each covering every plan; the
+// arguments and block-prefix tables go through plans[0]'s in-scatter
+// staging region. Each plan's blocks do exactly what they do in its own
+// launches (same pass, same XCD), so each grid is bitwise its own result.
+hipError_t launch_inscatter_batch(rte_plan *const *plans, int n, hipStream_t s)
+{
+    constexpr int kMaxPass = kScatFinalPass + 1;
+    std::vector<ScatArgs> sa(n);
+    // prefix tables: one per march pass, then the isotropic and the per-view reduce
+    std::vector<int> pre((size_t)(kMaxPass + 2) * (n + 1), 0);
+    int npass = 0;
+    for (int i = 0; i < n; ++i) {
+        sa[i] = scat_args(plans[i], nullptr);
+        npass = std::max(npass, scat_passes(sa[i]));
+    }
+    for (int t = 0; t < kMaxPass + 2; ++t) {
+        int *pt = pre.data() + (size_t)t * (n + 1);
+        for (int i = 0; i < n; ++i) {
+            const ScatArgs &a = sa[i];
+            const int64_t m3 = (int64_t)a.M * a.M * a.M;
+            const bool phase = scat_view_stride(plans[i]) != 0;
+            int nb = 0;
+            if (t < kMaxPass) nb = t < scat_passes(a) ? scat_pass_blocks(a, t) : 0;
+            else if (t == kMaxPass) nb = phase ? 0 : (int)((m3 + kReduceBlock - 1) / kReduceBlock);
+            else nb = phase ? blocks_for(m3) * plans[i]->V : 0;
+            pt[i + 1] = pt[i] + nb;  // march block counts are multiples of 8
+        }
+    }
+    rte_plan *p0 = plans[0];
+    const size_t o_a = p0->scat_stage_off, o_p = (o_a + sizeof(ScatArgs) * n + 15) & ~(size_t)15;
+    const size_t bytes = o_p + sizeof(int) * pre.size() - o_a;
+    if (o_a + bytes > p0->scat_stage_off + p0->scat_stage_bytes) return hipErrorInvalidValue;
+    // the pinned region is rewritten only after its previous upload ended
+    hipError_t e = hipEventSynchronize(p0->scat_event);
+    if (e != hipSuccess) return e;
+    char *h = static_cast<char *>(p0->h_batch);
+    std::memcpy(h + o_a, sa.data(), sizeof(ScatArgs) * n);
+    std::memcpy(h + o_p, pre.data(), sizeof(int) * pre.size());
+    char *d = static_cast<char *>(p0->d_batch);
+    e = hipMemcpyAsync(d + o_a, h + o_a, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(p0->scat_event, s);
+    if (e != hipSuccess) return e;
+    const ScatArgs *dsa = reinterpret_cast<const ScatArgs *>(d + o_a);
+    const int *dpre = reinterpret_cast<const int *>(d + o_p);
+    const int C = p0->params.channels;
+    for (int t = 0; t < kMaxPass + 2; ++t) {
+        const int total = pre[(size_t)t * (n + 1) + n];
+        if (total == 0) continue;
+        const int *pt = dpre + (size_t)t * (n + 1);
+        if (t < kMaxPass) {
+            if (C == 3) hipLaunchKernelGGL(inscatter_march_batch_kernel<3>, dim3(total), dim3(kBlock), 0, s, dsa, pt, n, t);
+            else hipLaunchKernelGGL(inscatter_march_batch_kernel<1>, dim3(total), dim3(kBlock), 0, s, dsa, pt, n, t);
+        } else if (t == kMaxPass) {
+            if (C == 3) hipLaunchKernelGGL(inscatter_reduce_batch_kernel<3>, dim3(total), dim3(kReduceBlock), 0, s, dsa, pt, n);
+            else hipLaunchKernelGGL(inscatter_reduce_batch_kernel<1>, dim3(total), dim3(kReduceBlock), 0, s, dsa, pt, n);
+        } else {
+            if (C == 3) hipLaunchKernelGGL(inscatter_phase_reduce_batch_kernel<3>, dim3(total), dim3(kBlock), 0, s, dsa, pt, n);
+            else hipLaunchKernelGGL(inscatter_phase_reduce_batch_kernel<1>, dim3(total), dim3(kBlock), 0, s, dsa, pt, n);
+        }
     }
     return hipGetLastError();
 }

@@ -240,3 +240,47 @@ def test_serving_loop_matches_sequential(budget, lanes):
         assert torch.equal(a.result, b.result), a.jid
     s = serve.latency_summary(jobs)
     assert s["jobs"] == 12 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_batched_inscatter_steps_match_each_job_alone():
+    """Jobs with in-scattering: a step computes every plan's in-scatter grid
+    with one launch per march pass and reduce. A volume beyond one slab (the
+    slab-per-XCD schedule, five passes), two small one-pass volumes with
+    other grid resolutions and direction counts, and a Henyey-Greenstein plan
+    (per-view grids) advance in ragged groups; each result is bitwise its
+    result alone (rte_reconstruct, per-plan launches)."""
+    import torch
+    say("batched in-scatter vs alone")
+    cfgs = [dict(n=96, views=3, W=40, H=36, M=12, dirs=16, g=0.0),
+            dict(n=24, views=4, W=36, H=36, M=8, dirs=12, g=0.0),
+            dict(n=20, views=2, W=32, H=30, M=6, dirs=9, g=0.0),
+            dict(n=22, views=3, W=30, H=28, M=7, dirs=10, g=0.5)]
+    plans, inputs = [], []
+    try:
+        for i, c in enumerate(cfgs):
+            spec = small_spec(i, c["n"], c["views"], c["W"], c["H"])
+            plans.append(rte().Plan(spec.grid, spec.rig, channels=3, step_vox=0.5, albedo=0.3,
+                                    scatter_res=c["M"], scatter_dirs=c["dirs"], phase_g=c["g"]))
+            em, sig = synth.video_frame(spec, 2)
+            emd, sgd = dev(em), dev(sig)
+            S = plans[-1].inscatter(emd, sgd)
+            inputs.append((plans[-1].render(emd, sgd, S), sgd))
+        alone = []
+        for p, (F, sig) in zip(plans, inputs):
+            out = torch.zeros((3,) + p.vol_shape, device="cuda")
+            p.reconstruct(F, sig, out, 4)
+            alone.append(out)
+        for p, (F, sig) in zip(plans, inputs):
+            p.job_begin(F, sig, torch.zeros((3,) + p.vol_shape, device="cuda"))
+        # four steps per plan; the first plan of a step (whose region stages the
+        # in-scatter arguments) varies
+        for group in ([0, 1], [2, 0, 3], [1, 2, 3, 0], [3, 1], [0, 2], [1, 3, 2]):
+            rte().job_step([plans[i] for i in group])
+        for i, (a, p) in enumerate(zip(alone, plans)):
+            out = torch.empty((3,) + p.vol_shape, device="cuda")
+            p.job_end(out)
+            torch.cuda.synchronize()
+            assert torch.equal(a, out), i
+    finally:
+        for p in plans:
+            p.close()
