@@ -125,13 +125,16 @@ def test_full_size_gradient_against_finite_differences():
     h = 1e-3 on 64 random voxels inside the flame (32 emission, 32 extinction).
 
     Emission differences only change the perturbed samples, so they are
-    checked entry by entry. An extinction perturbation changes the
-    transmittance of everything behind it: the FP32 rounding of the two full
-    renders then enters the difference at about 1% of it per entry (the
-    per-pixel change is ~1e-5 of the pixel value), so at h = 1e-3 the 32
-    entries are checked jointly (least-squares slope and correlation), and
-    entry by entry at h = 1e-2 where that noise is ten times smaller and the
-    truncation error is still ~(h/sigma)^2."""
+    checked entry by entry at h = 1e-3. An extinction perturbation changes the
+    transmittance of everything behind it, so the FP32 rounding of the two
+    re-rendered images enters the difference divided by 2h. Measured on these
+    32 entries, the median deviation from the adjoint gradient falls as 1/h
+    (3.0e-2 at h = 1e-3, 8.6e-3 at 4e-3, 4.4e-3 at 1e-2): rounding noise, not a
+    gradient or truncation error, which would stay or grow with h. So the
+    extinction entries are checked jointly at h = 4e-3 (least-squares slope
+    within 1e-2 and correlation >= 0.999, where the noise moves the slope by
+    about 1e-3), and entry by entry at h = 1e-2, where the truncation error
+    ~(h sigma Delta)^2 is still far below the tolerance."""
     import torch
     g, em_gt, sig_gt, rig = _full_size_case(12)
     say("full-size gradient FD")
@@ -169,19 +172,19 @@ def test_full_size_gradient_against_finite_differences():
             else:
                 idx = (z, yy, x)
                 gv = ds[idx].item()
-                s_fd.append(fd(sig, idx, 1e-3, False))
+                s_fd.append(fd(sig, idx, 4e-3, False))
                 s_an.append(gv)
                 s_err.append(abs(fd(sig, idx, 1e-2, False) - gv) / max(abs(gv), 1e-3 * float(ds.abs().max())))
     e_err, s_err = np.array(e_err), np.array(s_err)
     s_fd, s_an = np.array(s_fd), np.array(s_an)
     slope = float((s_fd * s_an).sum() / (s_an * s_an).sum())
     r = float(np.corrcoef(s_fd, s_an)[0, 1])
-    # per-entry noise of the h = 1e-3 extinction differences is a few percent,
-    # so the slope over 32 entries is known to about 1% (one standard error)
+    # per-entry rounding noise of the h = 4e-3 extinction differences is
+    # about 1%, so the slope over 32 entries is known to about 1e-3
     report = dict(emission_max=float(e_err.max()), slope=slope, r=r,
                   sigma_h1e2_median=float(np.median(s_err)), sigma_h1e2_max=float(s_err.max()))
     assert e_err.max() <= 1e-2, report
-    assert abs(slope - 1.0) <= 3e-2 and r >= 0.995, report
+    assert abs(slope - 1.0) <= 1e-2 and r >= 0.999, report
     assert np.median(s_err) <= 5e-3 and s_err.max() <= 3e-2, report
 
 
