@@ -1,4 +1,4 @@
-"""GPU parity at the two full-size workloads the benchmark times, on the same
+"""GPU parity at the full-size workloads the benchmark times, on the same
 seeded inputs, against the FP64 oracle (Sec. 3.3; render tolerance per view
 and channel, reconstruction tolerance after the fixed iteration counts).
 
@@ -8,6 +8,10 @@ and channel, reconstruction tolerance after the fixed iteration counts).
   zero against the oracle's frames.
 * temperature: 128^3 temperature field, 8 views of 512x512, 30 iterations of
   the temperature fit from 800 K against the oracle's frames.
+* the colour workload with Henyey-Greenstein in-scattering (g = 0.5): every
+  view's in-scatter grid and render.
+* the differentiable workload's forward model: 256^3 RGB + extinction with
+  single scattering, 12 views of 1024x768: in-scatter grid and render.
 
 The oracle needs a few seconds per iteration on the host's cores, so each
 long run is cut into chunks of iterations (one test each, sharing the state
@@ -132,3 +136,42 @@ def advance_temperature(upto):
 @pytest.mark.parametrize("upto", [15, 30])
 def test_temperature_workload_fit_matches_oracle(upto):
     advance_temperature(upto)
+
+
+def test_colour_hg_workload_inscatter_and_render_match_oracle():
+    """The colour workload with Henyey-Greenstein in-scattering (g = 0.5, one
+    in-scatter grid per view) at full size: every view's grid and the render
+    of every view and channel within the render tolerance of the oracle."""
+    c = colour()
+    say("headline colour, Henyey-Greenstein g = 0.5")
+    S_o = oracle.inscatter(c["g"], as64(c["em"]), as64(c["sig"]), s_res=M, n_dirs=DIRS, phase_g=0.5, rig=c["rig"])
+    F_o = oracle.render(c["g"], c["rig"], as64(c["em"]), as64(c["sig"]), step_vox=STEP, albedo=ALBEDO,
+                        inscatter=S_o)
+    with rte().Plan(c["g"], c["rig"], channels=3, step_vox=STEP, albedo=ALBEDO, scatter_res=M,
+                    scatter_dirs=DIRS, phase_g=0.5) as p:
+        S = host(p.inscatter(dev(c["em"]), dev(c["sig"])))
+        img = host(p.render(dev(c["em"]), dev(c["sig"]), dev(f32(S_o))))
+    assert S.shape == S_o.shape == (VIEWS, 3, M, M, M)
+    for v in range(VIEWS):
+        assert np.abs(S[v] - S_o[v]).max() / np.abs(S_o[v]).max() <= RENDER_REL, v
+    assert render_rel(img, F_o) <= RENDER_REL
+
+
+def test_differentiable_workload_render_matches_oracle():
+    """The differentiable workload's forward model at full size: 256^3 RGB
+    emission + extinction from 20 plume blobs, single scattering (albedo 0.3,
+    32^3 x 32 in-scatter grid), 12 views of 1024x768; the in-scatter grid and
+    the render of every view and channel within the render tolerance."""
+    g, em, sig = synth.colour_volume(0, n=256)
+    rig = synth.ring_rig(12, 1024, 768)
+    em, sig = f32(em), f32(sig)
+    say("headline differentiable forward, 256^3 x 12 x 1024x768")
+    S_o = oracle.inscatter(g, as64(em), as64(sig), s_res=M, n_dirs=DIRS)
+    F_o = oracle.render(g, rig, as64(em), as64(sig), step_vox=STEP, albedo=ALBEDO, inscatter=S_o)
+    with rte().Plan(g, rig, channels=3, step_vox=STEP, albedo=ALBEDO, scatter_res=M, scatter_dirs=DIRS,
+                    gradients=True) as p:
+        S = host(p.inscatter(dev(em), dev(sig)))
+        img, _ = p.render_forward(dev(em), dev(sig), dev(f32(S_o)))
+        img = host(img)
+    assert np.abs(S - S_o).max() / np.abs(S_o).max() <= RENDER_REL
+    assert render_rel(img, F_o) <= RENDER_REL
