@@ -2,8 +2,9 @@
 device memory) against the plan render it stands in for, through the C ABI:
 bitwise the same images on consecutive calls that share the library's static
 device array -- a large three-channel volume with in-scattering, then a
-smaller ragged one-channel volume, then a Henyey-Greenstein case with one
-in-scatter grid per view -- and no change of the device's free memory across
+smaller ragged one-channel volume, a Henyey-Greenstein case with one
+in-scatter grid per view, a rig whose rays all miss the box and cameras
+inside the volume -- and no change of the device's free memory across
 calls. The plan render itself is checked against the FP64 oracle elsewhere;
 here the first case is also compared with the oracle directly."""
 import numpy as np
@@ -43,13 +44,19 @@ CASES = {
     # Henyey-Greenstein in-scattering: one in-scatter grid per view
     "hg": dict(grid=synth.Grid(20, 18, 16), views=3, W=24, H=20, C=3, albedo=0.3, M=6, dirs=12, g=0.5,
                bg=0.0, seed=3),
+    # every ray misses the box: the images are the background
+    "miss": dict(grid=synth.Grid(12, 12, 12), views=2, W=16, H=12, C=3, albedo=0.0, M=0, dirs=32, g=0.0,
+                 bg=0.25, seed=4, rig=dict(radius=1.0, centre=(6.0, 6.0, 6.0))),
+    # cameras inside the volume
+    "inside": dict(grid=synth.Grid(16, 16, 16), views=3, W=20, H=18, C=1, albedo=0.0, M=0, dirs=32, g=0.0,
+                   bg=0.0, seed=5, rig=dict(radius=0.15, fov_y_deg=80.0)),
 }
 
 
 def inputs(name):
     c = CASES[name]
     g = c["grid"]
-    rig = synth.ring_rig(c["views"], c["W"], c["H"], elevation_jitter_deg=12, seed=c["seed"])
+    rig = synth.ring_rig(c["views"], c["W"], c["H"], elevation_jitter_deg=12, seed=c["seed"], **c.get("rig", {}))
     em, sig = blobs(g, c["C"], c["seed"])
     return c, g, rig, em, sig
 
@@ -71,7 +78,7 @@ def static_render(c, g, rig, em_d, sig_d, S, out):
 def test_static_render_equals_plan_render_on_consecutive_calls():
     import torch
     results = {}
-    for name in ("colour", "ragged", "hg"):
+    for name in ("colour", "ragged", "hg", "miss", "inside"):
         c, g, rig, em, sig = inputs(name)
         say("static render", name, g.nx, g.ny, g.nz, c["views"], c["W"], c["H"])
         em_d, sig_d = dev(em), dev(sig)
@@ -91,8 +98,10 @@ def test_static_render_equals_plan_render_on_consecutive_calls():
             F = oracle.render(g, rig, as64(em), as64(sig), step_vox=0.5, albedo=c["albedo"],
                               background=c["bg"], inscatter=S64)
             assert render_rel(got, F) <= RENDER_REL
+        if name == "miss":
+            assert np.all(got == np.float32(c["bg"]))
     # after the first call the array is resident: later calls change no free memory
-    for name in ("ragged", "hg"):
+    for name in ("ragged", "hg", "miss", "inside"):
         free0, free1, _ = results[name]
         assert free1 == free0, f"{name}: device free memory changed by {free0 - free1} bytes"
 
