@@ -129,6 +129,10 @@ Derived derive(const rte_grid *grid, const rte_camera *cams, int32_t ncams, cons
     return d;
 }
 
+// Rows of a tile in the per-sample buffers: its longest march rounded up to
+// whole groups of four samples.
+uint64_t group_rows(int kmax) { return ((uint64_t)kmax + rte::kGroup - 1) / rte::kGroup * rte::kGroup; }
+
 // Host estimate of the per-tile maximum segment count (same FP64 geometry as
 // the device ray table), used for the workspace bound before any device work.
 std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, const Derived &d)
@@ -380,7 +384,7 @@ size_t rte_plan_workspace_bytes(const rte_grid *grid, const rte_camera *cams, in
     const Derived d = derive(grid, cams, ncams, params);
     const std::vector<int> kmax = host_tile_kmax(grid, cams, d);
     uint64_t g = 0;
-    for (int k : kmax) g += (uint64_t)(k + 1) * rte::kTileRays;
+    for (int k : kmax) g += (uint64_t)group_rows(k + 1) * rte::kTileRays;
     return workspace(params, d, g).total;
 }
 
@@ -394,7 +398,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     const Derived d = derive(grid, cams, ncams, params);
     const std::vector<int> host_kmax = host_tile_kmax(grid, cams, d);
     uint64_t g_bound = 0;
-    for (int k : host_kmax) g_bound += (uint64_t)(k + 1) * rte::kTileRays;
+    for (int k : host_kmax) g_bound += (uint64_t)group_rows(k + 1) * rte::kTileRays;
     const Sizes bound = workspace(params, d, g_bound);
     if (hbm_budget_bytes && bound.total > hbm_budget_bytes)
         return fail(RTE_ERR_BUDGET, "plan needs up to %zu bytes, budget is %zu", bound.total, hbm_budget_bytes);
@@ -455,7 +459,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         if (kmax[t] > host_kmax[t] + 1)
             return bail(fail(RTE_ERR_HIP, "device ray table disagrees with the host bound at tile %d", t));
         off[t] = (uint32_t)g;
-        g += (uint64_t)kmax[t] * rte::kTileRays;
+        g += (uint64_t)group_rows(kmax[t]) * rte::kTileRays;
     }
     if (g > 0xFFFFFFFFull)
         return bail(fail(RTE_ERR_UNSUPPORTED, "%llu per-sample slots exceed the 2^32 a plan addresses; use fewer views "

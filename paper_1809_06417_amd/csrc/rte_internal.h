@@ -13,10 +13,15 @@
 namespace rte {
 
 // One wave64 marches one 8x8 pixel tile: a pixel tile is the unit of the
-// per-sample weight buffer ("g buffer"), laid out [tile][k][lane], so that the
-// 64 rays of a wave write one contiguous 256-byte row per march step.
+// per-sample weight buffer ("g buffer"), laid out [tile][k / 4][lane][k % 4]:
+// four consecutive samples of one ray sit in one 16-byte group, so that the
+// 64 rays of a wave write one contiguous 1 KB row every four march steps and
+// the back-projection fetches the samples a ray leaves in one voxel (one to
+// three at half-voxel steps) with one load. A tile holds kmax rounded up to a
+// multiple of kGroup rows.
 constexpr int kTile = 8;
 constexpr int kTileRays = kTile * kTile;
+constexpr int kGroup = 4;
 
 // Plan-free render (rte_render_static): its workspaces live in one static
 // device array of kStaticScratchBytes per GPU; at most kStaticMaxViews
@@ -90,8 +95,8 @@ struct rte_plan {
     uint32_t *d_tile_off = nullptr;  // per tile: first slot in d_g (plans keep < 2^32 slots)
     int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
     int n_active_tiles = 0;
-    float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k][lane]
-    float *d_q = nullptr;           // gradient plans: per-sample (g_k, q_k) float2 pairs, tile rows as d_g, sample k of a ray in row K - 1 - k
+    float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k / 4][lane][k % 4]
+    float *d_q = nullptr;           // gradient plans: per-sample (g_k, q_k) float2 pairs, [tile][K - 1 - k][lane] from the d_g tile offsets
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)
     float4 *d_scat = nullptr;       // packed in-scatter grid (rgb, 0)
     float4 *d_dirs = nullptr;       // in-scatter directions, voxel units per world unit

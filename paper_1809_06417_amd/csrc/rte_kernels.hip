@@ -628,8 +628,9 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     // optical depth so far, in FP64: an image render hands it to the reverse
     // march, which recovers every T_k from it even where T_K underflows
     double tau = 0.0;
-    float *gp = nullptr;
-    if constexpr (WRITE_G) gp = a.g + a.tile_off[tile] + lane;
+    // per-sample weights: stored as 16-byte groups of four steps
+    float4 *gp = nullptr;
+    if constexpr (WRITE_G) gp = reinterpret_cast<float4 *>(a.g + a.tile_off[tile]) + lane;
     ScatCorners scc;
     __shared__ typename Packed<C>::T win_lds[4][kWinSlots];
     VolWindow<C> win;
@@ -649,7 +650,8 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     }
     // all lanes step together up to the tile's longest march
     const int Kw = wave_max(K);
-    for (int k = 0; k < Kw; ++k) {
+    // one march step; returns the sample's weight g_k (0 past the ray's end)
+    auto step = [&](int k) -> float {
         const bool act = k < K;
         float s = 0.0f, len = 0.0f;
         if (act) segment_of(k, K, A.w, a.ds, s, len);
@@ -660,7 +662,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
         cell_of(y, a.ny, iy, fy);
         cell_of(z, a.nz, iz, fz);
         const bool in_win = win.update(act, ix, iy, iz, vr, a.nx, a.ny, a.nz, lane);
-        if (!act) continue;
+        if (!act) return 0.0f;
         float w[8];
         tri_weights(fx, fy, fz, w);
         float em[C], sig;
@@ -697,8 +699,22 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
             for (int c = 0; c < C; ++c) I[c] = fmaf(wg, em[c], I[c]);
         }
         Rsum += wg;
-        if constexpr (WRITE_G) gp[k * kTileRays] = wg;
         T *= e;
+        return wg;
+    };
+    if constexpr (WRITE_G) {
+        // four steps per group of the weight buffer, each weight computed
+        // into its place; the wave-uniform bounds keep every lane stepping
+        for (int k0 = 0; k0 < Kw; k0 += kGroup) {
+            float4 g4;
+            g4.x = step(k0);
+            g4.y = k0 + 1 < Kw ? step(k0 + 1) : 0.0f;
+            g4.z = k0 + 2 < Kw ? step(k0 + 2) : 0.0f;
+            g4.w = k0 + 3 < Kw ? step(k0 + 3) : 0.0f;
+            if (k0 < K) gp[(k0 / kGroup) * kTileRays] = g4;
+        }
+    } else {
+        for (int k = 0; k < Kw; ++k) step(k);
     }
     if constexpr (EPI == kEpiImage) {
         if (in_image) {
@@ -1408,7 +1424,15 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                     yv[0] = a.y[r];
                 }
             }
-            const float *gp = a.g + toff + ((py & 7) * 8 + (px & 7));
+            // weights of the candidate's samples: the group holding k_lo is
+            // loaded here, the next one only if the samples run into it
+            const uint32_t pl = (uint32_t)((py & 7) * 8 + (px & 7));
+            constexpr bool kGroups = MODE == kGatherAdjoint || MODE == kGatherAdjointCols;
+            const float4 *g4 = reinterpret_cast<const float4 *>(a.g);
+            const uint32_t gbase = toff / kGroup + pl;  // group 0 of this pixel, < 2^30
+            int gi = k_lo / kGroup;
+            float4 G = make_float4(0.f, 0.f, 0.f, 0.f);
+            if constexpr (kGroups) G = g4[gbase + (uint32_t)gi * kTileRays];
             for (int k = k_lo; k <= k_hi; ++k) {
                 float s, len;
                 segment_of(k, K, A.w, a.ds, s, len);
@@ -1440,11 +1464,18 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
                     float gk, qk = 0.0f;
                     if constexpr (MODE == kGatherGrad) {
                         // the adjoint march stores sample k in row K - 1 - k
-                        const float2 gq = reinterpret_cast<const float2 *>(a.q)[(gp - a.g) + (K - 1 - k) * kTileRays];
+                        const float2 gq = reinterpret_cast<const float2 *>(a.q)[toff + pl + (K - 1 - k) * kTileRays];
                         gk = gq.x;
                         qk = gq.y;
                     } else {
-                        gk = gp[k * kTileRays];
+                        if (k / kGroup != gi) {
+                            gi = k / kGroup;
+                            G = g4[gbase + (uint32_t)gi * kTileRays];
+                        }
+                        // two selects, no branches
+                        const float g01 = (k & 1) ? G.y : G.x;
+                        const float g23 = (k & 1) ? G.w : G.z;
+                        gk = (k & 2) ? g23 : g01;
                     }
                     float w[8];
                     tri_weights(fx, fy, fz, w);
