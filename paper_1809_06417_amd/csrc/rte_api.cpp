@@ -206,7 +206,11 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     // per-direction sums plus the slab-pass state (next sample, transmittance)
     s.scat_part = M ? sizeof(float) * (size_t)params->scatter_dirs * (C + 2) * M * M * M : sizeof(float);
     s.y = sizeof(float) * (size_t)d.n_rays * (C == 3 ? 4 : 1);  // per ray: float4 (RGB, pad) or float
-    s.part = sizeof(float) * 8 * (size_t)s.part_acc * std::max<int64_t>(d.n_part_cells, 1);
+    // back-projection partials: per gather brick, one plane of key points per
+    // accumulator; the visual hull keeps two 32-bit view masks per cell there
+    const int64_t bricks = std::max<int64_t>(d.n_part_cells / 256, 1);
+    s.part = sizeof(float) * std::max<size_t>((size_t)s.part_acc * rte::kBrickNodeStride * bricks,
+                                              2 * (size_t)std::max<int64_t>(d.n_part_cells, 1));
     s.cols = sizeof(float) * d.n_nodes;
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
     s.mask = sizeof(float) * (size_t)d.n_rays;

@@ -23,6 +23,14 @@ constexpr int kTile = 8;
 constexpr int kTileRays = kTile * kTile;
 constexpr int kGroup = 4;
 
+// The back-projection works on bricks of 8 x 8 x 4 cells and sums each
+// brick's corner contributions into the brick's 9 x 9 x 5 key points before
+// storing them: one plane of kBrickNodeStride floats (405 key points, padded
+// to a 128-byte multiple) per accumulator and brick.
+constexpr int kBrickNodesX = 9, kBrickNodesY = 9, kBrickNodesZ = 5;
+constexpr int kBrickNodes = kBrickNodesX * kBrickNodesY * kBrickNodesZ;
+constexpr int kBrickNodeStride = 416;
+
 // Plan-free render (rte_render_static): its workspaces live in one static
 // device array of kStaticScratchBytes per GPU; at most kStaticMaxViews
 // cameras, which travel in the kernel arguments.

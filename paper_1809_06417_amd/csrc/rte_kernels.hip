@@ -1337,7 +1337,9 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
     const int cx = bxi * 8 + (threadIdx.x & 7);
     const int cy = byi * 8 + ((threadIdx.x >> 3) & 7);
     const int cz = bzi * 4 + (threadIdx.x >> 6);
-    if (cx >= a.nx - 1 || cy >= a.ny - 1 || cz >= a.nz - 1) return;
+    // work-items past the grid's last cell gather nothing but stay for the
+    // brick's key-point sums
+    const bool valid = cx < a.nx - 1 && cy < a.ny - 1 && cz < a.nz - 1;
 
     float acc[8][NA];
 #pragma unroll
@@ -1351,7 +1353,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
     const int HW = a.W * a.H;
     uint64_t hull_bits = 0;
 
-    for (int v = a.view0; v < a.V; v += a.view_step) {
+    for (int v = a.view0; valid && v < a.V; v += a.view_step) {
         const float *P = a.proj[v].P;
         bool found = false;  // hull mode: this view already tags the cell
         // project the 8 corners of the padded box
@@ -1543,17 +1545,36 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, int b)
             }
         }
     }
-    // brick-major cell index: a wave stores 64 consecutive floats per plane
-    const int cell = b * kBlock + threadIdx.x;
     if constexpr (MODE == kGatherHull) {
+        // brick-major cell index: a wave stores 64 consecutive words per mask
+        const int cell = b * kBlock + threadIdx.x;
+        if (!valid) return;
         a.part[cell] = __uint_as_float((uint32_t)hull_bits);
         a.part[(int64_t)a.ncells + cell] = __uint_as_float((uint32_t)(hull_bits >> 32));
         return;
+    } else {
+        // sum the cells' corner contributions into the brick's key points in
+        // LDS: in pass e every cell adds its corner e (at offset (e & 1,
+        // e >> 1 & 1, e >> 2) from the cell), so no two work-items of a pass
+        // meet at one key point, and each key point takes its cells in the
+        // fixed order e = 0..7
+        __shared__ float nodes[NA * kBrickNodeStride];
+        for (int i = threadIdx.x; i < NA * kBrickNodeStride; i += kBlock) nodes[i] = 0.0f;
+        __syncthreads();
+        // the cell's own corner (0, 0, 0) in the brick's key points
+        const int n0 = ((cz - bzi * 4) * kBrickNodesY + (cy - byi * 8)) * kBrickNodesX + (cx - bxi * 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (valid) {
+                const int n = n0 + ((e >> 2) * kBrickNodesY + ((e >> 1) & 1)) * kBrickNodesX + (e & 1);
+#pragma unroll
+                for (int q = 0; q < NA; ++q) nodes[q * kBrickNodeStride + n] += acc[e][q];
+            }
+            __syncthreads();
+        }
+        float *out = a.part + (int64_t)b * NA * kBrickNodeStride;
+        for (int i = threadIdx.x; i < NA * kBrickNodeStride; i += kBlock) out[i] = nodes[i];
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) a.part[(int64_t)(c * NA + q) * a.ncells + cell] = acc[c][q];
 }
 
 // Waves per SIMD asked of the compiler: the three-channel adjoint gather
@@ -1598,8 +1619,8 @@ struct UpdateArgs {
     const float *lut;    // [3][lut_cap]
     int lut_cap, lut_size, fit_channel;
     float t_min, t_max;
-    int nx, ny, nz, ncells, acc;
-    int bx, by;  // gather bricks (8 x 8 x 4 cells) along x and y
+    int nx, ny, nz, acc;
+    int bx, by, bz;  // gather bricks (8 x 8 x 4 cells) along x, y and z
     int nbx, nby, nblocks;  // update bricks (8 x 8 x 4 key points) along x and y, and their count
     int64_t n;
     float lambda;
@@ -1621,13 +1642,14 @@ __device__ __forceinline__ float lut_invert(const float *row, int L, float x, fl
     return fmaf((float)lo + f, dT, t_min);
 }
 
-// Sum the 8 cells around key point j (fixed order: corner index of j in the
-// cell = dx + 2 dy + 4 dz) and apply the update rule.
+// Sum key point j's partials over the gather bricks that hold it and apply
+// the update rule.
 template <int C, int MODE>
 __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
 {
-    // one block per brick of 8 x 8 x 4 key points (the cell bricks of the
-    // gather, so the 8-cell reads of a wave are nearly contiguous)
+    // one block per brick of 8 x 8 x 4 key points: the key points of a
+    // gather brick less its upper faces, so a wave's first reads are one
+    // contiguous run of the brick's key-point plane
     if (blk >= a.nblocks) return;
     const int jx = (blk % a.nbx) * 8 + (threadIdx.x & 7);
     const int jy = ((blk / a.nbx) % a.nby) * 8 + ((threadIdx.x >> 3) & 7);
@@ -1639,14 +1661,19 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, int blk)
     float sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0f;
+    // the brick j falls in first, then (for j on a lower face, edge or
+    // corner of it) the bricks below along x, y and z, in a fixed order
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        const int cx = jx - (e & 1), cy = jy - ((e >> 1) & 1), cz = jz - ((e >> 2) & 1);
-        if (cx < 0 || cy < 0 || cz < 0 || cx > a.nx - 2 || cy > a.ny - 2 || cz > a.nz - 2) continue;
-        const int brick = ((cz >> 2) * a.by + (cy >> 3)) * a.bx + (cx >> 3);
-        const int cell = brick * kBlock + (((cz & 3) * 8 + (cy & 7)) * 8 + (cx & 7));
+        const int ox = e & 1, oy = (e >> 1) & 1, oz = e >> 2;
+        const int gx = (jx >> 3) - ox, gy = (jy >> 3) - oy, gz = (jz >> 2) - oz;
+        const int lx = (jx & 7) + 8 * ox, ly = (jy & 7) + 8 * oy, lz = (jz & 3) + 4 * oz;
+        if (lx >= kBrickNodesX || ly >= kBrickNodesY || lz >= kBrickNodesZ) continue;
+        if (gx < 0 || gy < 0 || gz < 0 || gx >= a.bx || gy >= a.by || gz >= a.bz) continue;
+        const int64_t plane = (int64_t)((gz * a.by + gy) * a.bx + gx) * a.acc;
+        const int node = (lz * kBrickNodesY + ly) * kBrickNodesX + lx;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sum[q] += a.part[(int64_t)(e * a.acc + q) * a.ncells + cell];
+        for (int q = 0; q < NQ; ++q) sum[q] += a.part[(plane + q) * kBrickNodeStride + node];
     }
     if constexpr (MODE == kUpdDelta) {
 #pragma unroll
@@ -2389,9 +2416,9 @@ static UpdateArgs update_args(const rte_plan *p, int acc, float lambda, int clam
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
     a.nz = p->grid.nz;
-    a.ncells = (int)p->n_part_cells;
     a.bx = (p->grid.nx - 1 + 7) / 8;
     a.by = (p->grid.ny - 1 + 7) / 8;
+    a.bz = (p->grid.nz - 1 + 3) / 4;
     a.acc = acc;
     a.nbx = (p->grid.nx + 7) / 8;
     a.nby = (p->grid.ny + 7) / 8;
