@@ -179,6 +179,24 @@ def test_adjoint_identity_on_gpu(name):
     assert abs(lhs - rhs) <= 1e-5 * float(np.abs(Ax * as64(y)).sum())
 
 
+@pytest.mark.parametrize("step", [0.15, 1.7])
+@pytest.mark.parametrize("name", ["ragged", "colour_small"])
+def test_backproject_adjoint_other_steps(name, step):
+    """The per-sample weights are stored and read in groups of four samples of
+    a ray. A fine step leaves up to a dozen samples of one ray in a voxel (the
+    back-projection then walks across several groups); a coarse step leaves
+    most candidate rays of a voxel without a sample there. Both against the
+    oracle at the same step."""
+    c = case(name)
+    V, H, W = c["rig"].n_views, c["rig"].height, c["rig"].width
+    y = f32(np.random.default_rng(6).normal(size=(V, c["C"], H, W)))
+    ref = oracle.backproject_adjoint(c["g"], c["rig"], as64(c["sig"]), as64(y), step_vox=step)
+    say("backproject_adjoint_step", name, step)
+    with plan_for(c, step_vox=step) as p:
+        d = host(p.backproject(dev(c["sig"]), dev(y)))
+    assert rel_max(d, ref) <= BACKPROJ_REL
+
+
 @pytest.mark.parametrize("name", ["tiny", "ragged"])
 def test_backproject_paper_matches_oracle(name):
     c = case(name)
