@@ -133,11 +133,24 @@ Derived derive(const rte_grid *grid, const rte_camera *cams, int32_t ncams, cons
 // whole groups of four samples.
 uint64_t group_rows(int kmax) { return ((uint64_t)kmax + rte::kGroup - 1) / rte::kGroup * rte::kGroup; }
 
-// Host estimate of the per-tile maximum segment count (same FP64 geometry as
-// the device ray table), used for the workspace bound before any device work.
-std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, const Derived &d)
+// Host geometry of the tiles (same FP64 arithmetic as the device ray table):
+// the per-tile maximum segment count, used for the workspace bound before any
+// device work, and for the launch order each tile's sample count, the
+// K-weighted sum of its rays' chord midpoints, and per axis the distance all
+// samples travel along it.
+struct HostTiles {
+    std::vector<int> kmax;
+    std::vector<double> work;       // samples (sum of K over the tile's rays)
+    std::vector<double> mid[3];     // sum of K * chord midpoint, per axis
+    double travel[3] = {0.0, 0.0, 0.0};
+};
+
+HostTiles host_tiles(const rte_grid *grid, const rte_camera *cams, const Derived &d)
 {
-    std::vector<int> kmax(d.n_tiles, 0);
+    HostTiles h;
+    h.kmax.assign(d.n_tiles, 0);
+    h.work.assign(d.n_tiles, 0.0);
+    for (auto &m : h.mid) m.assign(d.n_tiles, 0.0);
     for (int v = 0; v < d.V; ++v) {
         const rte_camera &c = cams[v];
         double o[3];
@@ -167,12 +180,85 @@ std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, co
                 t0 = std::max(t0, 0.0);
                 if (!hit || !(t1 > t0)) continue;
                 const int K = (int)std::ceil((t1 - t0) / d.ds);
-                int &m = kmax[(size_t)v * d.tiles_per_view + (py / rte::kTile) * d.tiles_x + px / rte::kTile];
-                m = std::max(m, K);
+                const size_t t = (size_t)v * d.tiles_per_view + (py / rte::kTile) * d.tiles_x + px / rte::kTile;
+                h.kmax[t] = std::max(h.kmax[t], K);
+                h.work[t] += K;
+                for (int i = 0; i < 3; ++i) {
+                    h.mid[i][t] += K * (o[i] + dir[i] * inv * 0.5 * (t0 + t1));
+                    h.travel[i] += K * std::fabs(dir[i] * inv);
+                }
             }
     }
-    return kmax;
+    return h;
 }
+
+std::vector<int> host_tile_kmax(const rte_grid *grid, const rte_camera *cams, const Derived &d)
+{
+    return host_tiles(grid, cams, d).kmax;
+}
+
+// Launch slots of the render and the reverse march, four per block, block b
+// running on XCD b mod 8. The tiles that hold samples are cut into 8 bands of
+// equal sample count along the axis the samples travel least (for a ring of
+// cameras around an axis, bands of height), band x going to XCD x, so that
+// each XCD's L2 serves one band of the volume; each band runs its longest
+// marches first, and a band that runs out of tiles before the longest band
+// leaves its slots empty (-1; such a wave exits at once). The bands at the
+// volume's ends hold more, shorter tiles than the middle ones (about 1.7x on
+// a ring of cameras), so the slots come to about 1.4-1.6x the tiles; where
+// they would exceed twice the tiles, one list, longest march first, is dealt
+// to every XCD instead. Bands are used only for a packed volume of at most
+// kBandVolumeBytes: one beyond the last-level cache (256 MB) is better served
+// by every XCD marching the longest tiles, and so the same central part of
+// the volume, at the same time (a 268 MB volume: reverse march 7.4 -> 9.4 ms
+// with bands; a 33 MB one: render 0.655 -> 0.640 ms).
+// Tiles without samples follow; they only receive the background in image
+// renders. n_active: slots of the tiles with samples.
+constexpr size_t kBandVolumeBytes = 64ull << 20;
+
+std::vector<int32_t> tile_launch_order(const std::vector<int32_t> &kmax, const HostTiles &h, size_t vol_bytes,
+                                       int &n_active)
+{
+    const int n = (int)kmax.size();
+    auto longest = [&](int32_t a, int32_t b) { return kmax[a] > kmax[b]; };
+    std::vector<int32_t> act;
+    for (int t = 0; t < n; ++t)
+        if (kmax[t] > 0) act.push_back(t);
+    const int ax = (int)(std::min_element(h.travel, h.travel + 3) - h.travel);
+    auto work = [&](int32_t t) { return h.work[t] > 0.0 ? h.work[t] : (double)kmax[t]; };
+    auto key = [&](int32_t t) { return h.work[t] > 0.0 ? h.mid[ax][t] / h.work[t] : 0.0; };
+    std::vector<int32_t> by_key = act;
+    std::stable_sort(by_key.begin(), by_key.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+    double total = 0.0;
+    for (int32_t t : by_key) total += work(t);
+    std::vector<std::vector<int32_t>> band(8);
+    double run = 0.0;
+    for (int32_t t : by_key) {
+        band[std::min(7, (int)(8.0 * (run + 0.5 * work(t)) / std::max(total, 1.0)))].push_back(t);
+        run += work(t);
+    }
+    size_t rounds = 0;
+    for (auto &b : band) {
+        std::stable_sort(b.begin(), b.end(), longest);
+        rounds = std::max(rounds, (b.size() + 3) / 4);
+    }
+    std::vector<int32_t> order;
+    if (vol_bytes <= kBandVolumeBytes && 32 * rounds <= 2 * act.size() + 32) {
+        for (size_t i = 0; i < rounds; ++i)
+            for (int x = 0; x < 8; ++x)
+                for (size_t w = 0; w < 4; ++w) order.push_back(4 * i + w < band[x].size() ? band[x][4 * i + w] : -1);
+    } else {
+        order = act;
+        std::stable_sort(order.begin(), order.end(), longest);
+    }
+    n_active = (int)order.size();
+    for (int t = 0; t < n; ++t)
+        if (kmax[t] == 0) order.push_back(t);
+    return order;
+}
+
+// Launch slots a plan of n_tiles tiles can hold (see tile_launch_order).
+int64_t max_slots(int64_t n_tiles) { return 2 * n_tiles + 32; }
 
 struct Sizes {
     size_t cams, proj, rays, tnear, tiles, g, q, vol, scat, scat_part, dirs, dirs_world, y, part, cols, lut, mask,
@@ -215,7 +301,7 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
     s.lut = sizeof(float) * 3 * (size_t)s.lut_cap;
     s.mask = sizeof(float) * (size_t)d.n_rays;
     s.inside = sizeof(int32_t) * (size_t)d.n_nodes;
-    s.err = sizeof(float2) * (size_t)d.n_tiles + 2 * sizeof(double) + kBatchBytes;
+    s.err = sizeof(float2) * (size_t)max_slots(d.n_tiles) + 2 * sizeof(double) + kBatchBytes;
     s.total = s.cams + s.proj + s.rays + s.tnear + s.tiles + s.g + s.q + s.vol + s.scat + s.scat_part + s.dirs +
               s.dirs_world +
               s.y + s.part + s.cols + s.lut + s.mask + s.inside + s.err;
@@ -400,7 +486,8 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
     int rc = validate_config(grid, cams, ncams, params);
     if (rc) return rc;
     const Derived d = derive(grid, cams, ncams, params);
-    const std::vector<int> host_kmax = host_tile_kmax(grid, cams, d);
+    const HostTiles host = host_tiles(grid, cams, d);
+    const std::vector<int> &host_kmax = host.kmax;
     uint64_t g_bound = 0;
     for (int k : host_kmax) g_bound += (uint64_t)group_rows(k + 1) * rte::kTileRays;
     const Sizes bound = workspace(params, d, g_bound);
@@ -469,16 +556,10 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         return bail(fail(RTE_ERR_UNSUPPORTED, "%llu per-sample slots exceed the 2^32 a plan addresses; use fewer views "
                                               "or a coarser step", (unsigned long long)g));
     p->g_floats = g;
-    // launch order of the render: tiles that hold samples, longest march first
-    // (stable, so equal tiles keep their spatial order); tiles without
-    // samples follow, they only receive the background in image renders
-    std::vector<int32_t> order;
-    for (int t = 0; t < d.n_tiles; ++t)
-        if (kmax[t] > 0) order.push_back(t);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return kmax[a] > kmax[b]; });
-    p->n_active_tiles = (int)order.size();
-    for (int t = 0; t < d.n_tiles; ++t)
-        if (kmax[t] == 0) order.push_back(t);
+    // launch order of the render and the reverse march
+    const size_t vol_bytes = (params->channels == 3 ? 16 : 8) * (size_t)d.n_nodes;
+    const std::vector<int32_t> order = tile_launch_order(kmax, host, vol_bytes, p->n_active_slots);
+    p->n_slots = (int)order.size();
     if ((rc = dev_alloc(&p->d_tile_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1), acc)))
         return bail(rc);
     if (hipMemcpyAsync(p->d_tile_off, off.data(), sizeof(uint32_t) * d.n_tiles, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -498,7 +579,7 @@ int rte_plan_create(rte_plan **out, const rte_grid *grid, const rte_camera *cams
         (rc = dev_alloc(&p->d_y, full.y, acc)) || (rc = dev_alloc(&p->d_part, full.part, acc)) ||
         (rc = dev_alloc(&p->d_cols, full.cols, acc)) || (rc = dev_alloc(&p->d_lut, full.lut, acc)) ||
         (rc = dev_alloc(&p->d_mask, full.mask, acc)) || (rc = dev_alloc(&p->d_inside, full.inside, acc)) ||
-        (rc = dev_alloc(&p->d_err, sizeof(float2) * (size_t)d.n_tiles, acc)) ||
+        (rc = dev_alloc(&p->d_err, sizeof(float2) * (size_t)p->n_slots, acc)) ||
         (rc = dev_alloc(&p->d_err_sum, 2 * sizeof(double), acc)))
         return bail(rc);
     if ((rc = dev_alloc(&p->d_batch, kBatchBytes, acc))) return bail(rc);

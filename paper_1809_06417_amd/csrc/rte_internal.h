@@ -101,8 +101,9 @@ struct rte_plan {
     float *d_tnear = nullptr;       // entry distance (export only)
     int32_t *d_tile_kmax = nullptr;
     uint32_t *d_tile_off = nullptr;  // per tile: first slot in d_g (plans keep < 2^32 slots)
-    int32_t *d_tile_order = nullptr; // all tiles: those with samples (heaviest first), then empty ones
-    int n_active_tiles = 0;
+    int32_t *d_tile_order = nullptr; // launch slots: tiles with samples (per-XCD bands, -1 for an empty slot), then tiles without
+    int n_active_slots = 0;         // slots of the tiles with samples
+    int n_slots = 0;                // all slots (entries of d_tile_order and of d_err)
     float *d_g = nullptr;           // per-sample weights T_k Delta_k phi_k, [tile][k / 4][lane][k % 4]
     float *d_q = nullptr;           // gradient plans: per-sample (g_k, q_k) float2 pairs, [tile][K - 1 - k][lane] from the d_g tile offsets
     float *d_vol = nullptr;         // packed volume: float4 (C = 3) or float2 (C = 1)

@@ -599,6 +599,10 @@ __device__ __forceinline__ void render_body(const RenderArgs &a, int blk)
     // every lane of the wave reads the same entry: keep the tile (and so the
     // view and the per-view in-scatter grid address) in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(a.tile_order[slot]);
+    if (tile < 0) {  // an empty slot of an XCD's band
+        if (a.err && lane == 0) a.err[slot] = make_float2(0.0f, 0.0f);
+        return;
+    }
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     if (a.sub_n > 1 && v % a.sub_n != a.sub_s) return;  // whole wave: view outside the subset
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
@@ -833,6 +837,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_march_kernel(GradArgs a)
     // every lane of the wave reads the same entry: keep the tile (and so the
     // view and the per-view in-scatter grid address) in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(a.tile_order[slot]);
+    if (tile < 0) return;  // an empty slot of an XCD's band
     const int v = tile / a.tiles_per_view, t = tile - v * a.tiles_per_view;
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
@@ -2061,7 +2066,7 @@ static RenderArgs render_args(const rte_plan *p, int epilogue, const float *fram
     // an image needs every pixel (misses get the background); residuals and
     // weights are only ever read for rays that hold samples
     // (the image error of the stop rule also needs the pixels of empty tiles)
-    a.n_launch = (epilogue == kEpiImage || err) ? p->n_tiles : p->n_active_tiles;
+    a.n_launch = (epilogue == kEpiImage || err) ? p->n_slots : p->n_active_slots;
     a.nb8 = (a.n_launch + 3) / 4;
     a.nx = p->grid.nx;
     a.ny = p->grid.ny;
@@ -2279,7 +2284,7 @@ hipError_t launch_adjoint_march(const rte_plan *p, bool use_scatter, const doubl
     a.rayB = p->d_rayB;
     a.tile_off = p->d_tile_off;
     a.tile_order = p->d_tile_order;
-    a.n_launch = p->n_active_tiles;
+    a.n_launch = p->n_active_slots;
     a.vol = p->d_vol;
     a.scat = p->d_scat;
     a.scat_vstride = scat_view_stride(p);
@@ -2520,7 +2525,7 @@ hipError_t launch_apply_outside(const rte_plan *p, int channels, const int32_t *
 
 hipError_t launch_err_reduce(const rte_plan *p, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(err_reduce_kernel, dim3(1), dim3(kBlock), 0, s, p->d_err, p->n_tiles, out);
+    hipLaunchKernelGGL(err_reduce_kernel, dim3(1), dim3(kBlock), 0, s, p->d_err, p->n_slots, out);
     return hipGetLastError();
 }
 
@@ -2542,7 +2547,8 @@ static hipError_t step_batch(rte_plan *const *plans, int n, bool scat, hipStream
         ga[i] = gather_args(p, p->d_y, q.alpha_l, q.alpha_d, q.tau, nullptr, q.g_sigma, q.seed, p->job_iter);
         ua[i] = update_args(p, C, q.lambda, q.clamp_nonneg, nullptr, nullptr, 0, 0, nullptr,
                             q.use_hull ? p->d_inside : nullptr);
-        rp[i + 1] = rp[i] + ra[i].nb8;
+        // each plan's render blocks start on XCD 0, as when launched alone
+        rp[i + 1] = rp[i] + grid8(ra[i].nb8);
         gp[i + 1] = gp[i] + ga[i].bx * ga[i].by * ga[i].bz;
         up[i + 1] = up[i] + ua[i].nblocks;
     }
@@ -2686,7 +2692,7 @@ hipError_t launch_render_static(rte_plan *view, const rte_camera *cams, const fl
     view->d_tile_order = reinterpret_cast<int32_t *>(b + L.order);
     view->d_vol = reinterpret_cast<float *>(b + L.vol);
     view->d_scat = M ? reinterpret_cast<float4 *>(b + L.scat) : nullptr;
-    view->n_active_tiles = view->n_tiles;
+    view->n_active_slots = view->n_slots = view->n_tiles;
     // every byte the render reads is written earlier in this call: nothing
     // in the array has to start at zero
     StaticCams sc{};
