@@ -180,6 +180,28 @@ def roofline_record(dom: str, avg_s: float, alg_bytes: int, n_units: int, worklo
     return out
 
 
+def step_spread(step_fn, fresh, steps, repeats):
+    """The timed steps run again `repeats` times (each from the same start,
+    after the main measurement): median and 5th/95th percentiles of the time
+    per step over the repeats. Reported beside `ms_per_step`, never in place
+    of it."""
+    import numpy as np
+    import torch
+    if repeats <= 0:
+        return None
+    per_step = []
+    for _ in range(repeats):
+        x = fresh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step_fn(x, steps)
+        torch.cuda.synchronize()
+        per_step.append((time.perf_counter() - t0) / steps * 1e3)
+    q = np.percentile(per_step, [5, 50, 95])
+    return {"repeats": repeats, "steps_each": steps, "p5": round(float(q[0]), 4), "p50": round(float(q[1]), 4),
+            "p95": round(float(q[2]), 4)}
+
+
 def cpu_baseline(g, rig, em, sig, frames, wl, views):
     """The FP64 oracle (as it stands) on a bounded sample: one iteration of the
     same loop (in-scatter grid, render, back-projection) restricted to the
@@ -246,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU baseline sample (one FP64 iteration)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="after the timed steps: time the same steps again this many times for the spread")
     ap.add_argument("--hbm-budget-gib", type=int, default=64, help="serve: workspace budget for resident plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter scale)")
@@ -349,6 +373,7 @@ def main():
     ktimes = {k: plan.kernel_time(k) for k in rte.KERNELS}
     plan.set_timing(False)
     print(f"[bench] timed {args.steps} steps in {elapsed * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    spread = step_spread(step_fn, fresh, args.steps, args.repeats)
 
     samples = plan.samples
     value = samples * args.steps / elapsed
@@ -417,6 +442,7 @@ def main():
                    "frames_per_s": args.steps / elapsed / wl["iters"]},
         "roofline": roofline,
         "cpu_baseline": base,
+        "step_ms_spread": spread,
         "kernels": per_kernel,
     }
     print(json.dumps(out))

@@ -62,3 +62,20 @@ def test_compulsory_floor():
     # packed RGB + extinction read once per view, frames once, the update written once
     assert mod.compulsory_floor(n, 3, 8, 512, 512) == 8 * n * 16 + 8 * 3 * 512 * 512 * 4 + 3 * n * 4
     assert mod.compulsory_floor(n, 1, 8, 512, 512) == 8 * n * 8 + 8 * 512 * 512 * 4 + n * 4
+
+
+def test_step_spread_percentiles_over_repeats(bench, monkeypatch):
+    """The spread reruns the timed steps `repeats` times, each from a fresh
+    start, and reports per-step percentiles; no repeats gives no record."""
+    import torch
+    mod, _ = bench
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    clock = iter([0.0, 0.010, 1.0, 1.030, 2.0, 2.020])  # 10, 30, 20 ms for 10 steps each
+    monkeypatch.setattr(mod.time, "perf_counter", lambda: next(clock))
+    starts, calls = [], []
+    rec = mod.step_spread(lambda x, k: calls.append((x, k)), lambda: starts.append(1) or "x0", 10, 3)
+    assert calls == [("x0", 10)] * 3 and len(starts) == 3
+    assert rec["repeats"] == 3 and rec["steps_each"] == 10
+    assert rec["p50"] == pytest.approx(2.0)
+    assert rec["p5"] == pytest.approx(1.0 + 0.1 * 1.0) and rec["p95"] == pytest.approx(3.0 - 0.1 * 1.0)
+    assert mod.step_spread(None, None, 10, 0) is None
