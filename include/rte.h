@@ -422,6 +422,14 @@ enum {
 int rte_plan_set_timing(rte_plan *plan, int32_t enable);
 int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);
 
+/* Timing of some kernels only: bit k of `kernels` brackets the launches of
+ * RTE_KERNEL k with events (each event adds a marker of a few microseconds to
+ * the stream, so a measurement that needs one kernel's duration times only
+ * that kernel); 0 turns timing off, and rte_plan_set_timing(plan, 1) equals
+ * all bits set. Resets the totals like rte_plan_set_timing. Bits at or above
+ * RTE_KERNEL_COUNT: RTE_ERR_INVALID_ARG. */
+int rte_plan_set_timing_mask(rte_plan *plan, uint32_t kernels);
+
 /* Message for the last non-zero return on this thread ("" if none). */
 const char *rte_last_error(void);
 

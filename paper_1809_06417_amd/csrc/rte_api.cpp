@@ -312,9 +312,27 @@ Sizes workspace(const rte_render_params *params, const Derived &d, uint64_t g_fl
 
 hipEvent_t take_event(rte_plan *p);
 
-void drain_timing(rte_plan *p)
+// Timing events only measure: they skip the system-scope fence a default
+// event performs when it is recorded (a cache writeback and invalidation that
+// would also slow the launch after it).
+hipEvent_t make_timing_event()
 {
-    for (auto &r : p->pending) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Adds the finished launches' times and returns their events to the pool;
+// wait = false leaves launches still running in `pending` (no host wait).
+void drain_timing(rte_plan *p, bool wait = true)
+{
+    size_t kept = 0;
+    for (size_t i = 0; i < p->pending.size(); ++i) {
+        const auto r = p->pending[i];
+        if (!wait && hipEventQuery(r.stop) != hipSuccess) {
+            p->pending[kept++] = r;
+            continue;
+        }
         float ms = 0.0f;
         if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
             p->kernel_ms[r.kernel] += ms;
@@ -323,17 +341,15 @@ void drain_timing(rte_plan *p)
         p->event_pool.push_back(r.start);
         p->event_pool.push_back(r.stop);
     }
-    p->pending.clear();
+    p->pending.resize(kept);
 }
 
+// An event for the next launch: from the pool, else from the launches that
+// have finished, else a new one (the host never waits on the GPU here).
 hipEvent_t take_event(rte_plan *p)
 {
-    if (p->event_pool.empty()) drain_timing(p);
-    if (p->event_pool.empty()) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
+    if (p->event_pool.empty()) drain_timing(p, false);
+    if (p->event_pool.empty()) return make_timing_event();
     hipEvent_t e = p->event_pool.back();
     p->event_pool.pop_back();
     return e;
@@ -347,14 +363,14 @@ struct Timed {
     hipEvent_t e0 = nullptr;
     Timed(rte_plan *p_, int k, hipStream_t s_) : p(p_), kernel(k), s(s_)
     {
-        if (p->timing) {
+        if ((p->timing_mask >> kernel) & 1u) {
             e0 = take_event(p);
             if (e0) hipEventRecord(e0, s);
         }
     }
     hipError_t done(hipError_t launch_status)
     {
-        if (p->timing && e0) {
+        if (e0) {
             hipEvent_t e1 = take_event(p);
             if (e1) {
                 hipEventRecord(e1, s);
@@ -1091,11 +1107,14 @@ int rte_job_step(rte_plan *const *plans, int32_t n, void *stream)
     // timing of the batched launches is charged to the first plan of the batch
     rte_plan *p0t = rest[0];
     hipEvent_t marks[6] = {};
-    if (p0t->timing)
-        for (auto &m : marks) m = take_event(p0t);
-    hipError_t e = rte::launch_step_batch(rest, nrest, s, p0t->timing ? marks : nullptr);
-    if (p0t->timing) {
-        const int kid[3] = {RTE_KERNEL_RENDER, RTE_KERNEL_GATHER, RTE_KERNEL_UPDATE};
+    const int kid[3] = {RTE_KERNEL_RENDER, RTE_KERNEL_GATHER, RTE_KERNEL_UPDATE};
+    for (int k = 0; k < 3; ++k)
+        if ((p0t->timing_mask >> kid[k]) & 1u) {
+            marks[2 * k] = take_event(p0t);
+            marks[2 * k + 1] = take_event(p0t);
+        }
+    hipError_t e = rte::launch_step_batch(rest, nrest, s, p0t->timing_mask ? marks : nullptr);
+    if (p0t->timing_mask) {
         for (int k = 0; k < 3; ++k) {
             if (marks[2 * k] && marks[2 * k + 1]) {
                 p0t->pending.push_back({kid[k], marks[2 * k], marks[2 * k + 1]});
@@ -1192,23 +1211,29 @@ int rte_temperature_lut(rte_plan *plan, const rte_temp_params *temp, float *lut_
     return ok();
 }
 
-int rte_plan_set_timing(rte_plan *plan, int32_t enable)
+int rte_plan_set_timing_mask(rte_plan *plan, uint32_t kernels)
 {
     if (int rc = check_plan(plan)) return rc;
+    if (kernels >> RTE_KERNEL_COUNT) return fail(RTE_ERR_INVALID_ARG, "timing mask 0x%x names no kernel", kernels);
     drain_timing(plan);
-    plan->timing = enable != 0;
+    plan->timing_mask = kernels;
     for (int k = 0; k < RTE_KERNEL_COUNT; ++k) {
         plan->kernel_ms[k] = 0.0;
         plan->kernel_launches[k] = 0;
     }
-    if (plan->timing && plan->event_pool.empty()) {
+    if (plan->timing_mask && plan->event_pool.empty()) {
         for (int i = 0; i < 256; ++i) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return fail(RTE_ERR_HIP, "hipEventCreate failed");
+            hipEvent_t e = make_timing_event();
+            if (!e) return fail(RTE_ERR_HIP, "hipEventCreateWithFlags failed");
             plan->event_pool.push_back(e);
         }
     }
     return ok();
+}
+
+int rte_plan_set_timing(rte_plan *plan, int32_t enable)
+{
+    return rte_plan_set_timing_mask(plan, enable ? (1u << RTE_KERNEL_COUNT) - 1u : 0u);
 }
 
 int rte_plan_kernel_time(rte_plan *plan, int32_t kernel, double *total_ms, int64_t *launches)

@@ -143,7 +143,7 @@ struct rte_plan {
     std::vector<float> lut_host;
 
     // timing
-    bool timing = false;
+    uint32_t timing_mask = 0;  // bit k: launches of RTE_KERNEL k are bracketed by events
     std::vector<rte::TimingRecord> pending;
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[RTE_KERNEL_COUNT] = {0};

@@ -134,6 +134,7 @@ def lib():
     L.rte_flame_mask.argtypes = [vp, vp, ct.c_float, vp, vp]
     L.rte_visual_hull.argtypes = [vp, vp, vp, vp]
     L.rte_plan_set_timing.argtypes = [vp, i32]
+    L.rte_plan_set_timing_mask.argtypes = [vp, ct.c_uint32]
     L.rte_plan_kernel_time.argtypes = [vp, i32, P(ct.c_double), P(ct.c_int64)]
     L.rte_last_error.restype = ct.c_char_p
     _lib = L
@@ -412,8 +413,16 @@ class Plan:
                                          int(temp.lut_size)))
         return out
 
-    def set_timing(self, enable=True):
-        _check(lib().rte_plan_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable=True, kernels=None):
+        """Per-kernel timing on or off; `kernels` (names or RTE_KERNEL ids)
+        limits it to those kernels."""
+        if kernels is None:
+            _check(lib().rte_plan_set_timing(self._h, 1 if enable else 0))
+            return
+        mask = 0
+        for k in kernels:
+            mask |= 1 << (KERNELS[k] if isinstance(k, str) else int(k))
+        _check(lib().rte_plan_set_timing_mask(self._h, mask if enable else 0))
 
     def kernel_time(self, kernel):
         ms, n = ct.c_double(), ct.c_int64()

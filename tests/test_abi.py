@@ -106,6 +106,7 @@ def test_null_plan_calls_fail_cleanly():
     assert L.rte_backproject(None, None, None, None, 0, None, None) == rte.RTE_ERR_INVALID_ARG
     assert L.rte_reconstruct(None, None, None, None, 1, None, None) == rte.RTE_ERR_INVALID_ARG
     assert b"null plan" in L.rte_last_error()
+    assert L.rte_plan_set_timing_mask(None, 1) == rte.RTE_ERR_INVALID_ARG
     L.rte_plan_destroy(None)
 
 

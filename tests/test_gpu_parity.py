@@ -286,6 +286,27 @@ def test_warm_start_equals_continued_run():
     np.testing.assert_array_equal(a, b)
 
 
+def test_kernel_timing_mask_times_only_the_named_kernels():
+    """Timing limited to one kernel brackets only its launches; a mask
+    naming no kernel is rejected; timing everything counts every phase."""
+    c = case("tiny")
+    F = oracle_frames(c)
+    say("timing_mask", "tiny")
+    with plan_for(c) as p:
+        with pytest.raises(rte().RteError):
+            p.set_timing(True, kernels=[len(rte().KERNELS)])
+        x = dev(np.zeros_like(c["em"]))
+        p.set_timing(True, kernels=["gather"])
+        p.reconstruct(dev(F), dev(c["sig"]), x, 3)
+        assert p.kernel_time("gather")[1] == 3
+        assert p.kernel_time("render")[1] == 0 and p.kernel_time("update")[1] == 0
+        p.set_timing(True)
+        p.reconstruct(dev(F), dev(c["sig"]), x, 2)
+        assert p.kernel_time("render")[1] == 2 and p.kernel_time("gather")[1] == 2
+        assert p.kernel_time("update")[1] == 2 and p.kernel_time("gather")[0] > 0.0
+        p.set_timing(False)
+
+
 def test_determinism_bitwise():
     c = case("colour_small")
     F = oracle_frames(c)
