@@ -669,7 +669,8 @@ def run_serve(args, wl):
                                f"(grids 64-256^3, 4-12 views, 256^2-1024x768, RGB, no scattering), "
                                f"Poisson arrivals at {wl['rate']:g} jobs/s (and at {wl['sustainable_rate']:g} "
                                f"jobs/s), {wl['iters']} SART iterations per job warm-started from the "
-                               f"resident previous volume; batched loop on 2 stream lanes, 2 steps queued each",
+                               f"resident previous volume; batched loop on 2 stream lanes, 2 steps queued each, "
+                               f"a waiting job sharing the GPU with running ones once 3 wait",
                    "videos": {v: f"{s.grid.nx}^3, {s.rig.n_views} views of {s.rig.width}x{s.rig.height}, "
                                  f"{samples_of[v]} samples/iteration" for v, s in specs.items()},
                    "hbm_budget_gib": args.hbm_budget_gib, "plans_resident": plans_resident,

@@ -3,7 +3,10 @@
 Jobs (one video frame each: frames, the frame's extinction, a fixed number of
 SART iterations, warm-started from the video's previous result) arrive over
 time. The loop admits waiting jobs whenever their video is idle, a batch slot
-is free and the device memory the job needs fits the HBM budget: the video's
+is free, the device memory the job needs fits the HBM budget, and either
+nothing runs or a backlog has formed (at least `share_backlog` jobs wait;
+without one, sharing the GPU would lengthen the running jobs about as much as
+waiting lengthens the new one, so a lone arrival waits its turn): the video's
 plan workspace, its resident volume and the job's frames and extinction
 (idle plans are evicted, least recently used first; every video's latest
 volume stays resident on the device to warm-start its next frame).
@@ -104,11 +107,13 @@ def _zeros_volume(vs):
 
 
 def serve(videos, jobs, iters=10, hbm_budget_bytes=32 << 30, max_batch=64, keep_results=False,
-          clock=time.perf_counter, log=None, lanes=2, depth=2, stats=None):
+          clock=time.perf_counter, log=None, lanes=2, depth=2, stats=None, share_backlog=3):
     """Run `jobs` (sorted by arrival) through the continuous-batching loop.
     videos: {video id: VideoState}. Returns the jobs with start/done times.
     stats (a dict, optional) receives the GPU-busy fraction of the span (time
-    with at least one step or job end not yet complete) and the step count."""
+    with at least one step or job end not yet complete) and the step count.
+    share_backlog: a waiting job joins running ones only while at least this
+    many jobs wait (None: whenever it can)."""
     import torch
     need = min_budget(videos, jobs) if jobs else 0
     if need > hbm_budget_bytes:
@@ -158,6 +163,8 @@ def serve(videos, jobs, iters=10, hbm_budget_bytes=32 << 30, max_batch=64, keep_
         n_active = sum(len(lj) for lj in lane_jobs)
         for job in list(waiting):
             if n_active >= max_batch:
+                break
+            if share_backlog is not None and n_active > 0 and len(waiting) < share_backlog:
                 break
             vs = videos[job.video]
             if vs.busy:

@@ -193,17 +193,19 @@ def test_job_api_rejects_bad_batches():
         b.close()
 
 
-@pytest.mark.parametrize("budget, lanes", [("ample", 2), ("one_plan", 2), ("ample", 1), ("ample", 3)])
-def test_serving_loop_matches_sequential(budget, lanes):
+@pytest.mark.parametrize("budget, lanes, share", [("ample", 2, 3), ("one_plan", 2, 3), ("ample", 1, 3),
+                                                   ("ample", 3, 3), ("ample", 2, None), ("one_plan", 2, None)])
+def test_serving_loop_matches_sequential(budget, lanes, share):
     """The continuous-batching loop (on 1-3 stream lanes with steps queued
-    ahead, and with LRU eviction of idle plans when the HBM budget holds only
-    one plan besides the resident volumes) returns, per job, bitwise the
+    ahead, with LRU eviction of idle plans when the HBM budget holds only
+    one plan besides the resident volumes, sharing the GPU once three jobs
+    wait or whenever a job can be admitted) returns, per job, bitwise the
     volume of the one-job-at-a-time reference in arrival order."""
     import torch
     from paper_1809_06417_amd import serve
     arrivals = synth.poisson_arrivals(12, 400.0, seed=2)
     vids = np.random.default_rng(4).integers(0, len(SMALL), size=len(arrivals))
-    say("serving loop", budget, lanes)
+    say("serving loop", budget, lanes, share)
 
     def make_jobs():
         count = {}
@@ -226,7 +228,7 @@ def test_serving_loop_matches_sequential(budget, lanes):
     cap = serve.min_budget(videos, make_jobs()) if budget == "one_plan" else 1 << 34
     st = {}
     jobs = serve.serve(videos, make_jobs(), iters=4, hbm_budget_bytes=cap, keep_results=True, lanes=lanes,
-                       stats=st)
+                       stats=st, share_backlog=share)
     assert 0.0 < st["gpu_busy"] <= 1.01
     for v in videos.values():
         v.evict()
