@@ -275,6 +275,25 @@ def test_colour_with_inscatter_sart_matches_oracle():
         assert rel_rms(x[ch], ref[ch]) <= VOLUME_RMS
 
 
+@pytest.mark.parametrize("shape", [(2, 17, 9), (11, 2, 5)])
+def test_thin_grid_sart_matches_oracle(shape):
+    """Grids two nodes thick along one axis, with the other sizes putting
+    the last key points on a boundary between 8x8x4-cell bricks (17 nodes:
+    two bricks along y; 9 and 5 nodes: two and one brick layers along z):
+    the brick key-point sums and their assembly over neighbouring bricks at
+    their edges, through a whole RGB reconstruction, against the oracle."""
+    g = synth.Grid(*shape)
+    rig = synth.ring_rig(3, 30, 26, radius=2.4, elevation_jitter_deg=25, seed=3)
+    em, sig = blob_volume(g, 3, 5, n_blobs=3)
+    F = f32(oracle.render(g, rig, as64(em), as64(sig), step_vox=STEP))
+    ref = oracle.reconstruct(g, rig, as64(F), as64(sig), np.zeros(em.shape), 4, step_vox=STEP)
+    say("thin grid", shape)
+    with rte().Plan(g, rig, channels=3, step_vox=STEP) as p:
+        x = host(p.reconstruct(dev(F), dev(sig), dev(np.zeros(em.shape)), 4))
+    for ch in range(3):
+        assert rel_rms(x[ch], ref[ch]) <= VOLUME_RMS
+
+
 def test_warm_start_equals_continued_run():
     c = case("tiny")
     F = oracle_frames(c)
