@@ -202,10 +202,20 @@ def step_spread(step_fn, fresh, steps, repeats):
             "p95": round(float(q[2]), 4)}
 
 
-def cpu_baseline(g, rig, em, sig, frames, wl, views):
+def max_rel(a, b):
+    """max |a - b| / max |b| (0 when b is all zero)."""
+    import numpy as np
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    scale = float(np.abs(b).max()) if b.size else 0.0
+    return float(np.abs(a - b).max() / scale) if scale > 0 else 0.0
+
+
+def cpu_baseline(g, rig, em, sig, frames, wl, views, gpu=None):
     """The FP64 oracle (as it stands) on a bounded sample: one iteration of the
     same loop (in-scatter grid, render, back-projection) restricted to the
-    first `views` views."""
+    first `views` views. `gpu` (optional) holds the GPU's in-scatter grid and a
+    back-projection callable; after the timing, the GPU results on the same
+    inputs are compared with the oracle's (`accuracy`)."""
     import numpy as np
 
     import oracle
@@ -246,6 +256,20 @@ def cpu_baseline(g, rig, em, sig, frames, wl, views):
         oracle.set_num_threads(threads)
     out["single_thread"] = dict(value=int(K1.sum()) / dt1, unit="samples/s",
                                 sample=f"one view: {int(K1.sum())} samples in {dt1:.1f} s (in-scatter grid included)")
+    if gpu is not None:
+        # accuracy beside speed: the GPU's frames (its render of the benchmark's
+        # inputs) against the oracle's render, per view and channel; its
+        # in-scatter grid; and both back-projections of one FP32 residual
+        acc = {"render_max_rel_err": max(max_rel(frames[v, c], I[v, c]) for v in range(views)
+                                         for c in range(I.shape[1]))}
+        if S is not None and gpu.get("S") is not None and np.shape(gpu["S"]) == np.shape(S):
+            acc["inscatter_max_rel_err"] = max_rel(gpu["S"], S)
+        y32 = y.astype(np.float32)
+        d_orc = oracle.backproject_adjoint(g, sub, sig64, y32.astype(np.float64))
+        acc["backproject_max_rel_err"] = max_rel(gpu["backproject"](y32), d_orc)
+        acc["note"] = (f"GPU against the FP64 oracle on the benchmark's inputs, {views} of {rig.n_views} views; "
+                       f"relative to the oracle's largest value")
+        out["accuracy"] = acc
     return out
 
 
@@ -438,8 +462,18 @@ def main():
         if args.workload in ("temperature", "diff"):
             base = None
         else:
-            base = cpu_baseline(g, rig, em, sig, frames.cpu().numpy(), wl,
-                                min(args.cpu_views, wl["views"]))
+            nv = min(args.cpu_views, wl["views"])
+
+            def gpu_backproject(y32):
+                # the plan back-projects every view: the views outside the sample get 0
+                full = np.zeros((wl["views"],) + y32.shape[1:], np.float32)
+                full[:nv] = y32
+                d = plan.backproject(sigd, torch.from_numpy(full).cuda())
+                torch.cuda.synchronize()
+                return d.cpu().numpy()
+
+            gpu = {"S": S.cpu().numpy() if S is not None else None, "backproject": gpu_backproject}
+            base = cpu_baseline(g, rig, em, sig, frames.cpu().numpy(), wl, nv, gpu)
 
     out = {
         "metric": "ray samples/s per render+backproject iteration",

@@ -79,3 +79,10 @@ def test_step_spread_percentiles_over_repeats(bench, monkeypatch):
     assert rec["p50"] == pytest.approx(2.0)
     assert rec["p5"] == pytest.approx(1.0 + 0.1 * 1.0) and rec["p95"] == pytest.approx(3.0 - 0.1 * 1.0)
     assert mod.step_spread(None, None, 10, 0) is None
+
+
+def test_max_rel_is_relative_to_the_reference_maximum(bench):
+    mod, _ = bench
+    assert mod.max_rel([1.0, 2.0], [1.0, 2.0]) == 0.0
+    assert mod.max_rel([1.0, 2.5], [1.0, -2.0]) == pytest.approx(4.5 / 2.0)
+    assert mod.max_rel([1.0], [0.0]) == 0.0
