@@ -273,6 +273,36 @@ def cpu_baseline(g, rig, em, sig, frames, wl, views, gpu=None):
     return out
 
 
+def cpu_baseline_temperature(g, rig, frames, gpu_T1=None):
+    """The FP64 oracle's temperature fit (as it stands), one iteration from
+    800 K on all views of the temperature workload (colour-temperature map,
+    render of the fitted channel with row sums, back-projection with column
+    sums, EM update, LUT inverse); `gpu_T1` (optional), the GPU's result of the
+    same iteration, is compared with it."""
+    import numpy as np
+
+    import oracle
+    tp = oracle.TempParams()
+    lut = oracle.temp_lut(tp)
+    F = np.asarray(frames, np.float64)
+    _, _, K = oracle.ray_table(g, rig, 0.5)
+    samples = int(K.sum())
+    T0 = np.full(g.shape_zyx, 800.0)
+    t0 = time.perf_counter()
+    T1 = oracle.temperature_fit(g, rig, tp, lut, F, T0, 1)
+    dt = time.perf_counter() - t0
+    out = dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
+               sample=f"one FP64 iteration of the temperature fit on {rig.n_views} of {rig.n_views} views: "
+                      f"{samples} samples in {dt:.1f} s", cpu=cpu_model())
+    if gpu_T1 is not None:
+        d = np.abs(np.asarray(gpu_T1, np.float64) - T1)
+        out["accuracy"] = {"temperature_max_abs_err_K": float(d.max()),
+                           "temperature_rms_err_K": float(np.sqrt((d ** 2).mean())),
+                           "note": "GPU against the FP64 oracle after one iteration from 800 K on the "
+                                   "benchmark's frames"}
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -459,8 +489,13 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
-        if args.workload in ("temperature", "diff"):
+        if args.workload == "diff":
             base = None
+        elif args.workload == "temperature":
+            x1 = x0.clone()
+            plan.reconstruct_temperature(frames, x1, 1, tp)
+            torch.cuda.synchronize()
+            base = cpu_baseline_temperature(g, rig, frames.cpu().numpy(), x1.cpu().numpy())
         else:
             nv = min(args.cpu_views, wl["views"])
 
