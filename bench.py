@@ -303,6 +303,40 @@ def cpu_baseline_temperature(g, rig, frames, gpu_T1=None):
     return out
 
 
+def cpu_baseline_diff(g, rig, em0, sig0, S, frames, gpu_grad=None):
+    """The FP64 oracle's gradient (as it stands) on a bounded sample of the
+    differentiable workload: the loss 1/2 |I - F|^2 over view 0 only, at the
+    timed steps' starting point, forward render plus gradient with respect to
+    emission and extinction (the in-scatter grid held fixed, the GPU's, as in
+    the timed steps). `gpu_grad(dLdI)` (optional) gives the GPU's gradients of
+    the same loss for comparison."""
+    import numpy as np
+
+    import oracle
+    one = rig.subset([0])
+    em64, sig64 = np.asarray(em0, np.float64), np.asarray(sig0, np.float64)
+    S64 = np.asarray(S, np.float64)
+    F = np.asarray(frames[:1], np.float64)
+    _, _, K = oracle.ray_table(g, one, 0.5)
+    samples = int(K.sum())
+    kw = dict(step_vox=0.5, albedo=0.3, inscatter=S64)
+    t0 = time.perf_counter()
+    I = oracle.render(g, one, em64, sig64, **kw)
+    dLdI = I - F
+    d_em, d_sig = oracle.render_grad(g, one, em64, sig64, dLdI, **kw)
+    dt = time.perf_counter() - t0
+    out = dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
+               sample=f"one FP64 forward render and gradient on 1 of {rig.n_views} views: "
+                      f"{samples} samples in {dt:.1f} s", cpu=cpu_model())
+    if gpu_grad is not None:
+        ge, gs = gpu_grad(dLdI.astype(np.float32))
+        out["accuracy"] = {"grad_emission_max_rel_err": max_rel(ge, d_em),
+                           "grad_extinction_max_rel_err": max_rel(gs, d_sig),
+                           "note": "GPU against the FP64 oracle, same loss, view 0, relative to the oracle's "
+                                   "largest gradient"}
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -490,7 +524,18 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         if args.workload == "diff":
-            base = None
+            from paper_1809_06417_amd import autograd
+            em0, sg0 = (t.detach().cpu().numpy() for t in x0)
+
+            def gpu_grad(dldi0):
+                e = x0[0].clone().requires_grad_(True)
+                sg = x0[1].clone().requires_grad_(True)
+                img = autograd.render(plan, e, sg, S)
+                (img[0] * torch.from_numpy(dldi0[0]).cuda()).sum().backward()
+                torch.cuda.synchronize()
+                return e.grad.cpu().numpy(), sg.grad.cpu().numpy()
+
+            base = cpu_baseline_diff(g, rig, em0, sg0, S.cpu().numpy(), frames.cpu().numpy(), gpu_grad)
         elif args.workload == "temperature":
             x1 = x0.clone()
             plan.reconstruct_temperature(frames, x1, 1, tp)
